@@ -1,0 +1,623 @@
+/*
+ * lbm_oracle.c -- plain serial FP64 reference of the learned-collision
+ * lattice Boltzmann step (Ortali, Gabbana, Demo, Rozza, Toschi,
+ * "Kinetic data-driven approach to turbulence subgrid modeling",
+ * arXiv:2403.18466).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU library is
+ * checked against.  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it; the product path never does.  It shares
+ * no code, header, table or constant with the GPU library: every constant
+ * below is typed here from the paper (or from the stated reading where the
+ * paper is silent).
+ *
+ * State convention: canonical pre-collision populations stored as deviations
+ *   g_q(x) = f_q^pre(x) - w_q * rho0,
+ * layout [B][Q][nz][ny][nx], x fastest.  All arithmetic is double precision,
+ * node by node, in the order the paper states the method.
+ *
+ * One step (SI, "Numerical Method" and "Neural Network Architecture"):
+ *   moments      rho = sum f, rho u = sum f c                   (SI, moments)
+ *   equilibrium  2nd-order polynomial f^eq(rho, u)              (eq. feq)
+ *   BGK          Omega = -(1/tau)(f - f^eq), dt = 1             (eq. bgk-sm)
+ *   network      y = W3 tanh(W2 tanh(W1 g + b1) + b2) + b3      (SI, MLP)
+ *   update       Omega + (s_out/tau) y                          (eq. nn-model-full)
+ *   projection   remove the components along 1 and c_alpha      (SI, kappa layer)
+ *   forcing      f^eq(rho, u + F/rho) - f^eq(rho, u)            (eq. fext, EDM)
+ *   collide      f^post = f^pre + update + f^ext                (eq. lbe-sm)
+ *   stream       f^pre(x, t+1) = f^post(x - c, t), periodic     (stream/collide split)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Lattices                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* D3Q19, in the order and with the weights of Table S1. */
+static const int D3Q19_C[19][3] = {
+    {0, 0, 0},
+    {-1, 0, 0}, {0, -1, 0}, {0, 0, -1}, {0, 0, 1}, {0, 1, 0}, {1, 0, 0},
+    {-1, -1, 0}, {-1, 0, -1}, {-1, 0, 1}, {-1, 1, 0},
+    {0, -1, -1}, {0, -1, 1}, {0, 1, -1}, {0, 1, 1},
+    {1, -1, 0}, {1, 0, -1}, {1, 0, 1}, {1, 1, 0}};
+static const double D3Q19_W[19] = {
+    1.0 / 3.0,
+    1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+/* D2Q9.  The paper gives only D3Q19; this follows the same convention as
+ * Table S1: rest vector, then the axis vectors in lexicographic order, then
+ * the diagonals in lexicographic order.  Weights 4/9, 1/9, 1/36. */
+static const int D2Q9_C[9][3] = {
+    {0, 0, 0},
+    {-1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {1, 0, 0},
+    {-1, -1, 0}, {-1, 1, 0}, {1, -1, 0}, {1, 1, 0}};
+static const double D2Q9_W[9] = {
+    4.0 / 9.0,
+    1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+    1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+#define QMAX 19
+#define HMAX 512
+
+typedef struct {
+    int32_t lattice; /* 0 = D2Q9, 1 = D3Q19 */
+    int32_t nx, ny, nz, batch;
+    double tau, rho0;
+    int32_t force_kind; /* 0 none; 1 Kolmogorov Fx = A sin(2 pi k y / ny);
+                           2 the SI's three-component sine forcing */
+    double force_amp;
+    int32_t force_k;
+    int32_t hidden;     /* 0 = plain BGK */
+    int32_t quant;      /* 0 exact; 1 bf16; 2 fp16 rounding at the MLP operands */
+    double out_scale;   /* s_out: the network update is (s_out / tau) y */
+} orc_config;
+
+typedef struct {
+    int Q, D;
+    const int (*c)[3];
+    const double *w;
+} lattice_t;
+
+static int get_lattice(int id, lattice_t *L) {
+    if (id == 0) {
+        L->Q = 9; L->D = 2; L->c = D2Q9_C; L->w = D2Q9_W;
+        return 0;
+    }
+    if (id == 1) {
+        L->Q = 19; L->D = 3; L->c = D3Q19_C; L->w = D3Q19_W;
+        return 0;
+    }
+    return -1;
+}
+
+int orc_tables(int lattice, int *Q, int *D, int *c, double *w) {
+    lattice_t L;
+    if (get_lattice(lattice, &L)) return -1;
+    *Q = L.Q;
+    *D = L.D;
+    for (int q = 0; q < L.Q; ++q) {
+        for (int a = 0; a < 3; ++a) c[3 * q + a] = L.c[q][a];
+        w[q] = L.w[q];
+    }
+    return 0;
+}
+
+/* Number of packed parameters: [W1 (H x Q), b1 (H), W2 (H x H), b2 (H),
+ * W3 (Q x H), b3 (Q)], each matrix row-major [out][in]. */
+int64_t orc_param_elems(int lattice, int hidden) {
+    lattice_t L;
+    if (get_lattice(lattice, &L) || hidden <= 0) return 0;
+    int64_t Q = L.Q, H = hidden;
+    return H * Q + H + H * H + H + Q * H + Q;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rounding to a reduced-precision format, round-to-nearest-even.            */
+/* Used only in the emulated-quantisation mode: the value is rounded to the  */
+/* nearest number representable with `bits` significant bits (including the */
+/* implicit one) and the exponent range of the format, then kept in double. */
+/* ------------------------------------------------------------------------ */
+static double round_to_format(double v, int bits, int emin, double maxval) {
+    if (v == 0.0 || !isfinite(v)) return v;
+    int e;
+    frexp(v, &e);                  /* v = m 2^e, 0.5 <= |m| < 1 */
+    int ulp_exp = e - bits;        /* spacing of representable numbers */
+    int min_ulp_exp = emin - bits; /* subnormal spacing: 2^(emin-1) / 2^(bits-1) */
+    if (ulp_exp < min_ulp_exp) ulp_exp = min_ulp_exp;
+    double r = ldexp(nearbyint(ldexp(v, -ulp_exp)), ulp_exp); /* RNE */
+    if (fabs(r) > maxval) r = copysign(INFINITY, v);
+    return r;
+}
+
+/* `emin` is the frexp exponent of the smallest normal number (frexp writes
+ * v = m 2^e with 1/2 <= |m| < 1), so normal spacing is 2^(e - bits) and the
+ * subnormal spacing is 2^(emin - bits).
+ * bfloat16: 8 significant bits, smallest normal 2^-126 (emin = -125).
+ * binary16: 11 significant bits, smallest normal 2^-14 (emin = -13), largest 65504. */
+double orc_round_bf16(double v) { return round_to_format(v, 8, -125, 3.3895313892515355e38); }
+double orc_round_fp16(double v) { return round_to_format(v, 11, -13, 65504.0); }
+
+static double quantise(int quant, double v) {
+    if (quant == 1) return orc_round_bf16(v);
+    if (quant == 2) return orc_round_fp16(v);
+    return v;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-node physics                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Body force at integer node (x, y, z) of a field with the given sizes. */
+static void body_force(const orc_config *cfg, int x, int y, int z, double F[3]) {
+    F[0] = F[1] = F[2] = 0.0;
+    const double two_pi = 6.283185307179586476925286766559;
+    if (cfg->force_kind == 1) {
+        F[0] = cfg->force_amp * sin(two_pi * cfg->force_k * y / (double)cfg->ny);
+    } else if (cfg->force_kind == 2) {
+        /* SI, DNS set-up: Fx(y), Fy(z), Fz(x), each F sin(2 pi k s / L). */
+        F[0] = cfg->force_amp * sin(two_pi * cfg->force_k * y / (double)cfg->ny);
+        F[1] = cfg->force_amp * sin(two_pi * cfg->force_k * z / (double)cfg->nz);
+        F[2] = cfg->force_amp * sin(two_pi * cfg->force_k * x / (double)cfg->nx);
+    }
+}
+
+/* Equilibrium of eq. feq with c_s^2 = 1/3, written as a deviation from
+ * w rho0 and as a function of (drho = rho - rho0, momentum j = rho u):
+ *   f^eq_q - w_q rho0 = w_q [ drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 |u|^2) ]. */
+static void equilibrium_dev(const lattice_t *L, double rho0, double drho,
+                            const double j[3], double geq[]) {
+    double rho = rho0 + drho;
+    double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int q = 0; q < L->Q; ++q) {
+        double cu = L->c[q][0] * u[0] + L->c[q][1] * u[1] + L->c[q][2] * u[2];
+        geq[q] = L->w[q] * (drho + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    }
+}
+
+/* Per-node moments: drho = sum g, j = sum g c (the w rho0 part sums to 0). */
+static void node_moments(const lattice_t *L, const double g[], double *drho, double j[3]) {
+    double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    for (int q = 0; q < L->Q; ++q) {
+        s += g[q];
+        jx += g[q] * L->c[q][0];
+        jy += g[q] * L->c[q][1];
+        jz += g[q] * L->c[q][2];
+    }
+    *drho = s;
+    j[0] = jx; j[1] = jy; j[2] = jz;
+}
+
+/* Orthogonal projection onto the complement of span{1, c_x, c_y, c_z}
+ * (SI, kappa layer): v <- v + k1 + k2 c_x + k3 c_y + k4 c_z with
+ * k1 = -sum v / Q and k_{a+1} = -sum v c_a / sum c_a^2. */
+static void project(const lattice_t *L, double v[]) {
+    double s = 0.0, m[3] = {0, 0, 0}, n2[3] = {0, 0, 0};
+    for (int q = 0; q < L->Q; ++q) {
+        s += v[q];
+        for (int a = 0; a < 3; ++a) {
+            m[a] += v[q] * L->c[q][a];
+            n2[a] += (double)(L->c[q][a] * L->c[q][a]);
+        }
+    }
+    double k1 = -s / L->Q;
+    double k[3];
+    for (int a = 0; a < 3; ++a) k[a] = (n2[a] > 0) ? -m[a] / n2[a] : 0.0;
+    for (int q = 0; q < L->Q; ++q)
+        v[q] += k1 + k[0] * L->c[q][0] + k[1] * L->c[q][1] + k[2] * L->c[q][2];
+}
+
+/* Parameter views into the packed buffer. */
+typedef struct {
+    const double *W1, *b1, *W2, *b2, *W3, *b3;
+} mlp_view;
+
+static mlp_view mlp_unpack(const double *theta, int Q, int H) {
+    mlp_view m;
+    m.W1 = theta;
+    m.b1 = m.W1 + (int64_t)H * Q;
+    m.W2 = m.b1 + H;
+    m.b2 = m.W2 + (int64_t)H * H;
+    m.W3 = m.b2 + H;
+    m.b3 = m.W3 + (int64_t)Q * H;
+    return m;
+}
+
+/* Saved forward quantities of one node, needed by the adjoint. */
+typedef struct {
+    double g[QMAX];
+    double drho, j[3], F[3];
+    double x0[QMAX];
+    double h1[HMAX], h2[HMAX];     /* activations after tanh (and rounding) */
+    double t1[HMAX], t2[HMAX];     /* tanh values before rounding */
+    double y[QMAX];
+} node_fwd;
+
+/* The MLP of the SI (three linear layers, two hidden activations), with the
+ * activation tanh.  Weights are the (optionally rounded) packed parameters. */
+static void mlp_forward(const orc_config *cfg, const lattice_t *L, const mlp_view *p,
+                        node_fwd *s) {
+    int Q = L->Q, H = cfg->hidden, qt = cfg->quant;
+    for (int i = 0; i < Q; ++i) s->x0[i] = quantise(qt, s->g[i]);
+    for (int o = 0; o < H; ++o) {
+        double a = p->b1[o];
+        for (int i = 0; i < Q; ++i) a += quantise(qt, p->W1[(int64_t)o * Q + i]) * s->x0[i];
+        s->t1[o] = tanh(a);
+        s->h1[o] = quantise(qt, s->t1[o]);
+    }
+    for (int o = 0; o < H; ++o) {
+        double a = p->b2[o];
+        for (int i = 0; i < H; ++i) a += quantise(qt, p->W2[(int64_t)o * H + i]) * s->h1[i];
+        s->t2[o] = tanh(a);
+        s->h2[o] = quantise(qt, s->t2[o]);
+    }
+    for (int o = 0; o < Q; ++o) {
+        double a = p->b3[o];
+        for (int i = 0; i < H; ++i) a += quantise(qt, p->W3[(int64_t)o * H + i]) * s->h2[i];
+        s->y[o] = a;
+    }
+}
+
+/* Collision of one node: post = g + P(Omega_BGK + (s_out/tau) y) + f^ext. */
+static void collide_node(const orc_config *cfg, const lattice_t *L, const double *theta,
+                         node_fwd *s, double post[]) {
+    int Q = L->Q;
+    double geq[QMAX], upd[QMAX];
+    node_moments(L, s->g, &s->drho, s->j);
+    equilibrium_dev(L, cfg->rho0, s->drho, s->j, geq);
+    for (int q = 0; q < Q; ++q) upd[q] = -(s->g[q] - geq[q]) / cfg->tau;
+    if (cfg->hidden > 0) {
+        mlp_view p = mlp_unpack(theta, Q, cfg->hidden);
+        mlp_forward(cfg, L, &p, s);
+        double k = cfg->out_scale / cfg->tau;
+        for (int q = 0; q < Q; ++q) upd[q] += k * s->y[q];
+    }
+    project(L, upd);
+    double fext[QMAX];
+    for (int q = 0; q < Q; ++q) fext[q] = 0.0;
+    if (s->F[0] != 0.0 || s->F[1] != 0.0 || s->F[2] != 0.0) {
+        double rho = cfg->rho0 + s->drho;
+        double js[3] = {s->j[0] + s->F[0], s->j[1] + s->F[1], s->j[2] + s->F[2]};
+        double e0[QMAX], e1[QMAX];
+        (void)rho;
+        equilibrium_dev(L, cfg->rho0, s->drho, s->j, e0);
+        equilibrium_dev(L, cfg->rho0, s->drho, js, e1); /* u + F/rho = (j + F)/rho */
+        for (int q = 0; q < Q; ++q) fext[q] = e1[q] - e0[q];
+    }
+    for (int q = 0; q < Q; ++q) post[q] = s->g[q] + upd[q] + fext[q];
+}
+
+static int check_cfg(const orc_config *cfg, lattice_t *L) {
+    if (get_lattice(cfg->lattice, L)) return -1;
+    if (cfg->nx <= 0 || cfg->ny <= 0 || cfg->nz <= 0 || cfg->batch <= 0) return -1;
+    if (L->D == 2 && cfg->nz != 1) return -1;
+    if (cfg->hidden < 0 || cfg->hidden > HMAX) return -1;
+    return 0;
+}
+
+static inline int64_t wrap(int64_t i, int64_t n) {
+    int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+/* One full step (collide at every node, then periodic streaming), on
+ * canonical pre-collision deviations.  g_out must not alias g_in. */
+int orc_step(const orc_config *cfg, const double *theta, const double *g_in, double *g_out) {
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q;
+    int64_t N = nx * ny * nz;
+    node_fwd *s = (node_fwd *)malloc(sizeof(node_fwd));
+    if (!s) return -2;
+    for (int64_t b = 0; b < cfg->batch; ++b) {
+        const double *gi = g_in + b * Q * N;
+        double *go = g_out + b * Q * N;
+        for (int64_t z = 0; z < nz; ++z)
+            for (int64_t y = 0; y < ny; ++y)
+                for (int64_t x = 0; x < nx; ++x) {
+                    int64_t n = (z * ny + y) * nx + x;
+                    for (int q = 0; q < Q; ++q) s->g[q] = gi[q * N + n];
+                    body_force(cfg, (int)x, (int)y, (int)z, s->F);
+                    double post[QMAX];
+                    collide_node(cfg, &L, theta, s, post);
+                    /* stream: f_q(x + c_q, t + 1) = f_q^post(x, t) */
+                    for (int q = 0; q < Q; ++q) {
+                        int64_t xd = wrap(x + L.c[q][0], nx);
+                        int64_t yd = wrap(y + L.c[q][1], ny);
+                        int64_t zd = wrap(z + L.c[q][2], nz);
+                        go[q * N + (zd * ny + yd) * nx + xd] = post[q];
+                    }
+                }
+    }
+    free(s);
+    return 0;
+}
+
+/* nsteps steps in place on g (uses one scratch copy). */
+int orc_run(const orc_config *cfg, const double *theta, double *g, int nsteps) {
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    int64_t total = (int64_t)cfg->batch * L.Q * cfg->nx * cfg->ny * cfg->nz;
+    double *tmp = (double *)malloc(sizeof(double) * total);
+    if (!tmp) return -2;
+    for (int t = 0; t < nsteps; ++t) {
+        int rc = orc_step(cfg, theta, g, tmp);
+        if (rc) { free(tmp); return rc; }
+        memcpy(g, tmp, sizeof(double) * total);
+    }
+    free(tmp);
+    return 0;
+}
+
+/* Post-collision populations of every node, without streaming (used by the
+ * tests to pin the collision alone). */
+int orc_collide(const orc_config *cfg, const double *theta, const double *g_in, double *post_out) {
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q, N = nx * ny * nz;
+    node_fwd *s = (node_fwd *)malloc(sizeof(node_fwd));
+    if (!s) return -2;
+    for (int64_t b = 0; b < cfg->batch; ++b)
+        for (int64_t z = 0; z < nz; ++z)
+            for (int64_t y = 0; y < ny; ++y)
+                for (int64_t x = 0; x < nx; ++x) {
+                    int64_t n = (z * ny + y) * nx + x;
+                    for (int q = 0; q < Q; ++q) s->g[q] = g_in[(b * Q + q) * N + n];
+                    body_force(cfg, (int)x, (int)y, (int)z, s->F);
+                    double post[QMAX];
+                    collide_node(cfg, &L, theta, s, post);
+                    for (int q = 0; q < Q; ++q) post_out[(b * Q + q) * N + n] = post[q];
+                }
+    free(s);
+    return 0;
+}
+
+/* Equilibrium initial state from a density and a velocity field:
+ * g_q = f^eq_q(rho, u) - w_q rho0 with j = rho u.
+ * rho: [B][nz][ny][nx]; u: [B][D][nz][ny][nx]. */
+int orc_init(const orc_config *cfg, const double *rho, const double *u, double *g) {
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    int64_t N = (int64_t)cfg->nx * cfg->ny * cfg->nz, Q = L.Q, D = L.D;
+    for (int64_t b = 0; b < cfg->batch; ++b)
+        for (int64_t n = 0; n < N; ++n) {
+            double r = rho[b * N + n];
+            double j[3] = {0, 0, 0};
+            for (int a = 0; a < D; ++a) j[a] = r * u[(b * D + a) * N + n];
+            double geq[QMAX];
+            equilibrium_dev(&L, cfg->rho0, r - cfg->rho0, j, geq);
+            for (int q = 0; q < Q; ++q) g[(b * Q + q) * N + n] = geq[q];
+        }
+    return 0;
+}
+
+/* Moments and diagnostics of canonical pre-collision populations.
+ * rho = rho0 + sum g; reported velocity u = (j + F/2) / rho (the usual EDM
+ * convention).  diag per field: [total mass, kinetic energy 1/2 sum rho|u|^2,
+ * number of nodes with a non-finite population, 0]. */
+int orc_moments(const orc_config *cfg, const double *g, double *rho, double *u, double *diag) {
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q, D = L.D, N = nx * ny * nz;
+    for (int64_t b = 0; b < cfg->batch; ++b) {
+        double mass = 0.0, ke = 0.0, bad = 0.0;
+        for (int64_t z = 0; z < nz; ++z)
+            for (int64_t y = 0; y < ny; ++y)
+                for (int64_t x = 0; x < nx; ++x) {
+                    int64_t n = (z * ny + y) * nx + x;
+                    double gq[QMAX];
+                    int finite = 1;
+                    for (int q = 0; q < Q; ++q) {
+                        gq[q] = g[(b * Q + q) * N + n];
+                        if (!isfinite(gq[q])) finite = 0;
+                    }
+                    double drho, j[3], F[3];
+                    node_moments(&L, gq, &drho, j);
+                    body_force(cfg, (int)x, (int)y, (int)z, F);
+                    double r = cfg->rho0 + drho;
+                    double uu = 0.0;
+                    for (int a = 0; a < D; ++a) {
+                        double ua = (j[a] + 0.5 * F[a]) / r;
+                        if (u) u[(b * D + a) * N + n] = ua;
+                        uu += ua * ua;
+                    }
+                    if (rho) rho[b * N + n] = r;
+                    if (!finite) { bad += 1.0; continue; }
+                    mass += r;
+                    ke += 0.5 * r * uu;
+                }
+        if (diag) {
+            diag[4 * b + 0] = mass;
+            diag[4 * b + 1] = ke;
+            diag[4 * b + 2] = bad;
+            diag[4 * b + 3] = 0.0;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of one step                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Reverse pass of collide_node.  mu = dL/d(post) of this node.  Adds
+ * dL/dg into lam (length Q) and dL/dtheta into dtheta.  The derivative is
+ * that of the exact-arithmetic map: rounding in the emulated mode is passed
+ * straight through. */
+static void collide_node_adjoint(const orc_config *cfg, const lattice_t *L, const double *theta,
+                                 node_fwd *s, const double mu[], double lam[], double *dtheta) {
+    int Q = L->Q;
+    double tau = cfg->tau, rho0 = cfg->rho0;
+    /* Forward recompute. */
+    double post[QMAX];
+    collide_node(cfg, L, theta, s, post);
+    double drho = s->drho, rho = rho0 + drho;
+    const double *j = s->j;
+    double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+
+    /* post = g + P(upd) + fext */
+    for (int q = 0; q < Q; ++q) lam[q] += mu[q];
+    double nu[QMAX];
+    for (int q = 0; q < Q; ++q) nu[q] = mu[q];
+    project(L, nu); /* P is symmetric */
+
+    /* upd = -(g - geq)/tau + (s_out/tau) y */
+    for (int q = 0; q < Q; ++q) lam[q] += -nu[q] / tau;
+    /* geq_q = w_q [drho + 3 c.j + (9/2 (c.j)^2 - 3/2 |j|^2) / rho] */
+    double Grho = 0.0, Gj[3] = {0, 0, 0};
+    for (int q = 0; q < Q; ++q) {
+        double a = nu[q] / tau; /* dL/dgeq_q */
+        double cu = L->c[q][0] * u[0] + L->c[q][1] * u[1] + L->c[q][2] * u[2];
+        Grho += a * L->w[q] * (1.0 - 4.5 * cu * cu + 1.5 * uu);
+        for (int al = 0; al < 3; ++al)
+            Gj[al] += a * L->w[q] * (3.0 * L->c[q][al] + 9.0 * cu * L->c[q][al] - 3.0 * u[al]);
+    }
+    /* fext_q = w_q [3 c.F + (9/2((c.(j+F))^2 - (c.j)^2) - 3/2(|j+F|^2 - |j|^2)) / rho] */
+    const double *F = s->F;
+    if (F[0] != 0.0 || F[1] != 0.0 || F[2] != 0.0) {
+        double jF[3] = {j[0] + F[0], j[1] + F[1], j[2] + F[2]};
+        double jj = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+        double jFjF = jF[0] * jF[0] + jF[1] * jF[1] + jF[2] * jF[2];
+        for (int q = 0; q < Q; ++q) {
+            double cj = L->c[q][0] * j[0] + L->c[q][1] * j[1] + L->c[q][2] * j[2];
+            double cjF = L->c[q][0] * jF[0] + L->c[q][1] * jF[1] + L->c[q][2] * jF[2];
+            double cF = L->c[q][0] * F[0] + L->c[q][1] * F[1] + L->c[q][2] * F[2];
+            double num = 4.5 * (cjF * cjF - cj * cj) - 1.5 * (jFjF - jj);
+            Grho += mu[q] * L->w[q] * (-num / (rho * rho));
+            for (int al = 0; al < 3; ++al)
+                Gj[al] += mu[q] * L->w[q] * (9.0 * cF * L->c[q][al] - 3.0 * F[al]) / rho;
+        }
+    }
+    for (int q = 0; q < Q; ++q)
+        lam[q] += Grho + Gj[0] * L->c[q][0] + Gj[1] * L->c[q][1] + Gj[2] * L->c[q][2];
+
+    if (cfg->hidden > 0) {
+        int H = cfg->hidden, qt = cfg->quant;
+        mlp_view p = mlp_unpack(theta, Q, H);
+        double *dW1 = dtheta, *db1 = dW1 + (int64_t)H * Q, *dW2 = db1 + H;
+        double *db2 = dW2 + (int64_t)H * H, *dW3 = db2 + H, *db3 = dW3 + (int64_t)Q * H;
+        double dy[QMAX], da2[HMAX], da1[HMAX];
+        double k = cfg->out_scale / tau;
+        for (int q = 0; q < Q; ++q) dy[q] = k * nu[q];
+        /* y = W3 h2 + b3 */
+        for (int o = 0; o < Q; ++o) {
+            db3[o] += dy[o];
+            for (int i = 0; i < H; ++i) dW3[(int64_t)o * H + i] += dy[o] * s->h2[i];
+        }
+        for (int i = 0; i < H; ++i) {
+            double d = 0.0;
+            for (int o = 0; o < Q; ++o) d += quantise(qt, p.W3[(int64_t)o * H + i]) * dy[o];
+            da2[i] = d * (1.0 - s->t2[i] * s->t2[i]); /* tanh' = 1 - tanh^2 */
+        }
+        /* h2 = tanh(W2 h1 + b2) */
+        for (int o = 0; o < H; ++o) {
+            db2[o] += da2[o];
+            for (int i = 0; i < H; ++i) dW2[(int64_t)o * H + i] += da2[o] * s->h1[i];
+        }
+        for (int i = 0; i < H; ++i) {
+            double d = 0.0;
+            for (int o = 0; o < H; ++o) d += quantise(qt, p.W2[(int64_t)o * H + i]) * da2[o];
+            da1[i] = d * (1.0 - s->t1[i] * s->t1[i]);
+        }
+        /* h1 = tanh(W1 x0 + b1), x0 = g */
+        for (int o = 0; o < H; ++o) {
+            db1[o] += da1[o];
+            for (int i = 0; i < Q; ++i) dW1[(int64_t)o * Q + i] += da1[o] * s->x0[i];
+        }
+        for (int i = 0; i < Q; ++i) {
+            double d = 0.0;
+            for (int o = 0; o < H; ++o) d += quantise(qt, p.W1[(int64_t)o * Q + i]) * da1[o];
+            lam[i] += d;
+        }
+    }
+}
+
+/* Adjoint of orc_step.  g_n: canonical state at step n; lam_n1 = dL/dg^{n+1};
+ * writes lam_n = dL/dg^n and adds dL/dtheta into dtheta (may be NULL when
+ * hidden == 0).  Streaming is a permutation, so its transpose reads
+ * lam^{n+1}_q(x + c_q). */
+int orc_step_adjoint(const orc_config *cfg, const double *theta, const double *g_n,
+                     const double *lam_n1, double *lam_n, double *dtheta) {
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q, N = nx * ny * nz;
+    int64_t P = orc_param_elems(cfg->lattice, cfg->hidden);
+    double *scratch_dtheta = NULL;
+    if (cfg->hidden > 0 && !dtheta) {
+        scratch_dtheta = (double *)calloc((size_t)P, sizeof(double));
+        if (!scratch_dtheta) return -2;
+        dtheta = scratch_dtheta;
+    }
+    node_fwd *s = (node_fwd *)malloc(sizeof(node_fwd));
+    if (!s) { free(scratch_dtheta); return -2; }
+    for (int64_t b = 0; b < cfg->batch; ++b)
+        for (int64_t z = 0; z < nz; ++z)
+            for (int64_t y = 0; y < ny; ++y)
+                for (int64_t x = 0; x < nx; ++x) {
+                    int64_t n = (z * ny + y) * nx + x;
+                    double mu[QMAX], lam[QMAX];
+                    for (int q = 0; q < Q; ++q) {
+                        int64_t xd = wrap(x + L.c[q][0], nx);
+                        int64_t yd = wrap(y + L.c[q][1], ny);
+                        int64_t zd = wrap(z + L.c[q][2], nz);
+                        mu[q] = lam_n1[(b * Q + q) * N + (zd * ny + yd) * nx + xd];
+                        s->g[q] = g_n[(b * Q + q) * N + n];
+                        lam[q] = 0.0;
+                    }
+                    body_force(cfg, (int)x, (int)y, (int)z, s->F);
+                    collide_node_adjoint(cfg, &L, theta, s, mu, lam, dtheta);
+                    for (int q = 0; q < Q; ++q) lam_n[(b * Q + q) * N + n] = lam[q];
+                }
+    free(s);
+    free(scratch_dtheta);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Velocity-MSE loss of the training configuration                           */
+/* ------------------------------------------------------------------------ */
+
+/* L = mean over fields, nodes and components of (u - u_target)^2 with
+ * u = (j + F/2)/rho of the canonical state g.  Writes dL/dg when dLdg is not
+ * NULL.  Returns L through *loss. */
+int orc_loss_velocity_mse(const orc_config *cfg, const double *g, const double *u_target,
+                          double *loss, double *dLdg) {
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q, D = L.D, N = nx * ny * nz;
+    double count = (double)cfg->batch * N * D;
+    double acc = 0.0;
+    for (int64_t b = 0; b < cfg->batch; ++b)
+        for (int64_t z = 0; z < nz; ++z)
+            for (int64_t y = 0; y < ny; ++y)
+                for (int64_t x = 0; x < nx; ++x) {
+                    int64_t n = (z * ny + y) * nx + x;
+                    double gq[QMAX], drho, j[3], F[3];
+                    for (int q = 0; q < Q; ++q) gq[q] = g[(b * Q + q) * N + n];
+                    node_moments(&L, gq, &drho, j);
+                    body_force(cfg, (int)x, (int)y, (int)z, F);
+                    double rho = cfg->rho0 + drho;
+                    double e[3] = {0, 0, 0}, u[3] = {0, 0, 0};
+                    for (int a = 0; a < D; ++a) {
+                        u[a] = (j[a] + 0.5 * F[a]) / rho;
+                        e[a] = u[a] - u_target[(b * D + a) * N + n];
+                        acc += e[a] * e[a];
+                    }
+                    if (dLdg) {
+                        /* du_a/dg_q = (c_qa - u_a) / rho */
+                        for (int q = 0; q < Q; ++q) {
+                            double d = 0.0;
+                            for (int a = 0; a < D; ++a) d += e[a] * (L.c[q][a] - u[a]);
+                            dLdg[(b * Q + q) * N + n] = 2.0 * d / (rho * count);
+                        }
+                    }
+                }
+    *loss = acc / count;
+    return 0;
+}
