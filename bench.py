@@ -1,0 +1,193 @@
+"""Throughput of the learned-collision lattice Boltzmann step on one MI355X.
+
+Workload: D2Q9 periodic 4096 x 4096, tau = 0.51, populations stored as
+float32 deviations f - w rho0, collision = BGK + (s_out/tau) * MLP 9->64->64->9
+(tanh; Glorot weights from seed 1, s_out = 2^-6) projected to conserve mass and
+momentum; initial velocity from the random-Fourier-mode recipe (|k| <= 4,
+max |u| = 0.05, seed 0).  One step = one stream-collide pass over the field
+(one kernel launch).  The headline runs the network on bf16 matrix cores with
+float32 accumulation; fp16, plain fp32 and plain BGK are timed at the same
+size for comparison.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N = 4096
+TAU = 0.51
+S_OUT = 2.0 ** -6
+HIDDEN = 64
+BYTES_PER_LUP = 72            # 9 float32 read + 9 float32 written per node
+TANH_PER_LUP = 2 * HIDDEN     # two hidden tanh layers
+TRANS_PER_TANH = 2            # exp2 + reciprocal: no tanh instruction exists
+HBM_PEAK = 8.0e12             # B/s, MI355X HBM3E
+# 256 CUs x 4 SIMDs x 8 transcendental lanes per clock x 2.4 GHz
+TRANS_PEAK = 256 * 4 * 8 * 2.4e9
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=200)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--variants", default="bf16,fp16,fp32,bgk")
+    return p.parse_args()
+
+
+def make_state(torch, lbm, inputs, L):
+    u = inputs.fourier_modes_velocity(N, N, kmax=4, umax=0.05, seed=0).astype("float32")
+    ud = torch.from_numpy(u).reshape(1, 2, 1, N, N).cuda()
+    rho = torch.ones((1, 1, N, N), dtype=torch.float32, device="cuda")
+    return L.init(rho, ud)
+
+
+def time_variant(torch, lbm, inputs, prec, hidden, steps, warmup, A0):
+    cfg = lbm.Config(nx=N, ny=N, tau=TAU, hidden=hidden, mlp_prec=prec, out_scale=S_OUT)
+    L = lbm.Lattice(cfg)
+    theta = None
+    if hidden:
+        theta = torch.from_numpy(inputs.glorot_params(9, hidden, seed=1)).cuda()
+    A = A0.clone()
+    B = torch.empty_like(A)
+    stream = torch.cuda.current_stream()
+    if warmup > 0:
+        lbm.lbm_step(L.ctx, cfg, A, B, theta, warmup, stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    out = lbm.lbm_step(L.ctx, cfg, A, B, theta, steps, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    _, _, diag = L.moments(out)
+    torch.cuda.synchronize()
+    d = diag.cpu().numpy()[0]
+    L.close()
+    return {"ms_per_step": ms, "mlups": N * N / (ms * 1e-3) / 1e6, "wall_s": wall,
+            "mass": float(d[0]), "kinetic_energy": float(d[1]), "nonfinite": int(d[2])}
+
+
+def cpu_baseline():
+    """The FP64 oracle on a bounded sample of the same workload: one step of
+    the same network on a 1024 x 1024 field (serial C, one host thread)."""
+    import numpy as np
+
+    import oracle
+    from paper_2403_18466_amd import inputs
+    n = 1024
+    cfg = oracle.Config(nx=n, ny=n, tau=TAU, hidden=HIDDEN, out_scale=S_OUT)
+    u = inputs.fourier_modes_velocity(n, n, kmax=4, umax=0.05, seed=0)
+    g = oracle.init_equilibrium(cfg, np.ones((1, 1, n, n)), u[None, :, None])
+    theta = inputs.glorot_params(9, HIDDEN, seed=1).astype(np.float64)
+    oracle.step(oracle.Config(nx=8, ny=8, tau=TAU, hidden=HIDDEN, out_scale=S_OUT),
+                np.zeros((1, 9, 1, 8, 8)), theta)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        g = oracle.step(cfg, g, theta)
+        steps += 1
+        if time.perf_counter() - t0 > 10.0 or steps >= 3:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} step(s) of the fp64 oracle on a {n}x{n} field of the same "
+                      f"workload (same network, tau, init recipe), serial C on one host thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(this build has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2403_18466_amd import inputs, lbm
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    lbm.load_library()
+    base = lbm.Lattice(lbm.Config(nx=N, ny=N, tau=TAU))
+    A0 = make_state(torch, lbm, inputs, base)
+    base.close()
+    torch.cuda.synchronize()
+
+    variants = {}
+    wanted = args.variants.split(",")
+    table = {"bf16": ("bf16", HIDDEN), "fp16": ("fp16", HIDDEN), "fp32": ("fp32", HIDDEN),
+             "bgk": ("fp32", 0)}
+    for name in ["bf16"] + [v for v in wanted if v != "bf16"]:
+        prec, hidden = table[name]
+        steps = args.steps if name != "fp32" else max(1, args.steps // 2)
+        variants[name] = time_variant(torch, lbm, inputs, prec, hidden, steps, args.warmup, A0)
+        print(f"# {name}: {variants[name]['ms_per_step']:.4f} ms/step, "
+              f"{variants[name]['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+
+    head = variants["bf16"]
+    t_launch = head["ms_per_step"] * 1e-3
+    trans_rate = TANH_PER_LUP * TRANS_PER_TANH * N * N / t_launch
+    hbm_rate = BYTES_PER_LUP * N * N / t_launch
+    roofline = {
+        "bound": "alu",
+        "achieved": trans_rate / 1e12,
+        "peak": TRANS_PEAK / 1e12,
+        "unit": "Ttrans/s",
+        "frac": trans_rate / TRANS_PEAK,
+        "traffic": None,
+        "hbm_achieved_GBps": hbm_rate / 1e9,
+        "hbm_frac": hbm_rate / HBM_PEAK,
+        "kernel": "nlbm_step_kernel<D2Q9, 64, bf16>",
+    }
+    bgk = variants.get("bgk")
+    result = {
+        "metric": "MLUPS of learned-collision LBM step (BF16 vs FP32) + % HBM/MFMA roofline",
+        "value": head["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "D2Q9 periodic 4096x4096 learned-collision throughput run, "
+                               "MLP 9->64->64->9 tanh, bf16 MFMA / fp32 accumulate, "
+                               "fp32 deviation populations, tau 0.51",
+                   "grid": [N, N], "hidden": HIDDEN, "tau": TAU, "out_scale": S_OUT},
+        "roofline": roofline,
+        "variants": {k: {"mlups": v["mlups"], "ms_per_step": v["ms_per_step"],
+                         "hbm_frac": BYTES_PER_LUP * N * N / (v["ms_per_step"] * 1e-3) / HBM_PEAK,
+                         "nonfinite": v["nonfinite"]} for k, v in variants.items()},
+    }
+    if "fp32" in variants:
+        result["bf16_over_fp32"] = head["mlups"] / variants["fp32"]["mlups"]
+    if bgk:
+        result["bgk_roofline"] = {"bound": "hbm", "achieved": BYTES_PER_LUP * N * N /
+                                  (bgk["ms_per_step"] * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9,
+                                  "unit": "GB/s",
+                                  "frac": BYTES_PER_LUP * N * N / (bgk["ms_per_step"] * 1e-3) /
+                                  HBM_PEAK}
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,481 @@
+// kernels_bwd.hpp -- adjoint (reverse-mode derivative) of one stream-collide
+// step, used to backpropagate a loss through unrolled time steps (SI,
+// "Unrolled training").
+//
+// One step maps the pull-shifted state A^n to A^{n+1}(x) = C(g(x)) with
+// g_q(x) = A^n_q(x - c_q) and C the node-local collision.  For
+// lam^{n+1} = dL/dA^{n+1} the adjoint is
+//   mu(x)  = lam^{n+1}(x)                    (local read),
+//   l(x)   = J_C(g(x))^T mu(x),              (node-local reverse pass)
+//   lam^n_q(x - c_q) = l_q(x)                (scatter: the transpose of the
+//                                             gather, a permutation),
+//   dtheta += sum_x (dC/dtheta)^T mu(x).
+// The reverse pass through C goes, in reverse order, through
+//   post = g + P(Omega + k y) + f^ext,   Omega = (f^eq(rho, j) - g)/tau,
+//   y = W3 h2 + b3, h2 = tanh(W2 h1 + b2), h1 = tanh(W1 g + b1),
+// with P the symmetric projector of the kappa layer, k = s_out/tau, and
+// tanh' = 1 - tanh^2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels_fwd.hpp"
+
+namespace lbm {
+
+// Reverse pass through everything except the network.  Given g and
+// mu = dL/dpost, returns nu = P mu and l = dL/dg without the network's
+// input gradient.
+template <class L>
+__device__ inline void collide_adjoint(const float g[L::Q], const float mu[L::Q], float rho0,
+                                       float omega, const float F[3], bool forced,
+                                       float nu[L::Q], float lam[L::Q]) {
+  constexpr int Q = L::Q;
+  float drho, j[3];
+  moments<L>(g, drho, j);
+  const float rho = rho0 + drho, inv = 1.f / rho;
+  const float u[3] = {j[0] * inv, j[1] * inv, j[2] * inv};
+  const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) nu[q] = mu[q];
+  project<L>(nu);
+  // d f^eq_q / d drho = w_q (1 - 9/2 (c.u)^2 + 3/2 |u|^2)
+  // d f^eq_q / d j_a  = w_q (3 c_a + 9 (c.u) c_a - 3 u_a)
+  float Gr = 0.f, Gj[3] = {0.f, 0.f, 0.f};
+  auto accum = [&](int q, float cu, float a) {
+    float wa = L::w[q] * a;
+    Gr += wa * (1.f - 4.5f * cu * cu + 1.5f * uu);
+    float s = wa * (3.f + 9.f * cu);
+    Gj[0] += (L::cx[q] > 0 ? s : (L::cx[q] < 0 ? -s : 0.f)) - 3.f * wa * u[0];
+    Gj[1] += (L::cy[q] > 0 ? s : (L::cy[q] < 0 ? -s : 0.f)) - 3.f * wa * u[1];
+    Gj[2] += (L::cz[q] > 0 ? s : (L::cz[q] < 0 ? -s : 0.f)) - 3.f * wa * u[2];
+  };
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    float cu = 0.f;
+    if (L::cx[q] > 0) cu += u[0];
+    if (L::cx[q] < 0) cu -= u[0];
+    if (L::cy[q] > 0) cu += u[1];
+    if (L::cy[q] < 0) cu -= u[1];
+    if (L::cz[q] > 0) cu += u[2];
+    if (L::cz[q] < 0) cu -= u[2];
+    accum(q, cu, omega * nu[q]);
+  }
+  if (forced) {
+    // f^ext_q = w_q rho [3 c.du + 9/2 c.du (2 c.u + c.du) - 3/2 du.(2u + du)],
+    // du = F/rho:  d/d drho = -w_q [9/2 c.du (2 c.u + c.du) - 3/2 du.(2u+du)],
+    //              d/d j_a  =  w_q (9 (c.du) c_a - 3 du_a).
+    const float du[3] = {F[0] * inv, F[1] * inv, F[2] * inv};
+    const float dd =
+        du[0] * (2.f * u[0] + du[0]) + du[1] * (2.f * u[1] + du[1]) + du[2] * (2.f * u[2] + du[2]);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      float cu = 0.f, cd = 0.f;
+      if (L::cx[q] > 0) { cu += u[0]; cd += du[0]; }
+      if (L::cx[q] < 0) { cu -= u[0]; cd -= du[0]; }
+      if (L::cy[q] > 0) { cu += u[1]; cd += du[1]; }
+      if (L::cy[q] < 0) { cu -= u[1]; cd -= du[1]; }
+      if (L::cz[q] > 0) { cu += u[2]; cd += du[2]; }
+      if (L::cz[q] < 0) { cu -= u[2]; cd -= du[2]; }
+      float wm = L::w[q] * mu[q];
+      Gr -= wm * (4.5f * cd * (2.f * cu + cd) - 1.5f * dd);
+      float s = 9.f * wm * cd;
+      Gj[0] += (L::cx[q] > 0 ? s : (L::cx[q] < 0 ? -s : 0.f)) - 3.f * wm * du[0];
+      Gj[1] += (L::cy[q] > 0 ? s : (L::cy[q] < 0 ? -s : 0.f)) - 3.f * wm * du[1];
+      Gj[2] += (L::cz[q] > 0 ? s : (L::cz[q] < 0 ? -s : 0.f)) - 3.f * wm * du[2];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    float d = Gr;
+    if (L::cx[q] > 0) d += Gj[0];
+    if (L::cx[q] < 0) d -= Gj[0];
+    if (L::cy[q] > 0) d += Gj[1];
+    if (L::cy[q] < 0) d -= Gj[1];
+    if (L::cz[q] > 0) d += Gj[2];
+    if (L::cz[q] < 0) d -= Gj[2];
+    lam[q] = mu[q] - omega * nu[q] + d;
+  }
+}
+
+// Scatter l to the pull-shifted positions: lam^n_q(x - c_q) = l_q(x).
+template <class L>
+__device__ inline void scatter(float* __restrict__ out, const Grid& G, int b, int x, int y, int z,
+                               const float v[L::Q]) {
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    int xd = wrap_sub(x, L::cx[q], G.nx), yd = wrap_sub(y, L::cy[q], G.ny),
+        zd = wrap_sub(z, L::cz[q], G.nz);
+    out[cell(G, b, q, L::Q, xd, yd, zd)] = v[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the BGK step (no network), one node per thread.
+// ---------------------------------------------------------------------------
+template <class L>
+__global__ __launch_bounds__(256) void bgk_backward_kernel(const float* __restrict__ A,
+                                                           const float* __restrict__ lam1,
+                                                           float* __restrict__ lam0, Grid G,
+                                                           Force Fc, float rho0, float omega,
+                                                           int nxc) {
+  const int row = blockIdx.x / nxc, xc = blockIdx.x - row * nxc;
+  const int x = xc * 256 + threadIdx.x;
+  if (x >= G.nx) return;
+  const int y = row % G.ny, t = row / G.ny, z = t % G.nz, b = t / G.nz;
+  float g[L::Q], mu[L::Q], nu[L::Q], lam[L::Q], F[3];
+  gather<L>(A, G, b, x, y, z, g);
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) mu[q] = lam1[cell(G, b, q, L::Q, x, y, z)];
+  body_force(Fc, G, x, y, z, F);
+  collide_adjoint<L>(g, mu, rho0, omega, F, Fc.kind != 0, nu, lam);
+  scatter<L>(lam0, G, b, x, y, z, lam);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the learned-collision step.
+//
+// Persistent wavefronts walk contiguous ranges of 64-node items as in the
+// forward kernel.  Per item: node layout gathers g, reads mu, and runs the
+// non-network part of the reverse pass; the network is recomputed and
+// differentiated on the matrix cores per 16-node group:
+//   forward   a1 = W1 x0 + b1, t1 = tanh a1;  a2 = W2 h1 + b2, t2 = tanh a2
+//   backward  dy = k nu;  d2 = (W3^T dy) (1 - t2^2);  d1 = (W2^T d2) (1 - t1^2);
+//             dx = W1^T d1
+//   weights   dW3 += dy h2^T, dW2 += d2 h1^T, dW1|db1 += d1 [x0|1]^T (MFMA with
+//             the node index as the contraction, operands transposed through
+//             LDS), db2 += sum d2, db3 += sum dy (lane sums).
+// Each wavefront writes its parameter-gradient partials (every entry, zeros
+// if it had no work) to part[wave][param]; grad_reduce_kernel sums them in a
+// fixed order.
+// ---------------------------------------------------------------------------
+constexpr unsigned bwd_blocks(int ncu) { return (unsigned)ncu; }
+
+template <class L, int H, int P>
+struct BwdLayout {
+  using S = Shape<L::Q, H>;
+  static constexpr int NF3 = S::HB * S::QB;   // W3^T fragments
+  static constexpr int NF2 = S::HB * S::HB;   // W2^T fragments
+  static constexpr int NF1 = S::KX * S::HB;   // W1^T fragments
+  static constexpr int NF = NF3 + NF2 + NF1;
+  static constexpr int SX = 16 * S::KX + 4;   // node-major tile stride (input / input grad)
+  static constexpr int SD = 16 * (S::QB > S::KX ? S::QB : S::KX) + 4;
+  static constexpr int ST = 20;               // feature-major transpose tile stride
+  static constexpr int per_wave = 64 * SX + 64 * SD + H * ST;
+};
+
+// Transpose of a 16x16 chunk in D layout (lane l: rows 4g + r of column i)
+// into the "node as contraction" operand layout (lane l: row i, columns
+// 4g + r), through a feature-major scratch tile T of stride ST.
+template <int ST>
+__device__ inline f4 transpose_chunk(float* T, int blk, f4 v, int lg, int li) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) T[(16 * blk + 4 * lg + r) * ST + li] = v[r];
+  wave_lds_sync();
+  f4 out = *reinterpret_cast<const f4*>(T + (16 * blk + li) * ST + 4 * lg);
+  return out;
+}
+
+template <class L, int H, int P>
+__global__ __launch_bounds__(256) void nlbm_backward_kernel(
+    const float* __restrict__ A, const float* __restrict__ theta, const float* __restrict__ lam1,
+    float* __restrict__ lam0, float* __restrict__ part, Grid G, Force Fc, float rho0,
+    float omega, float knn, int nitems, int nxc) {
+  using S = Shape<L::Q, H>;
+  using BL = BwdLayout<L, H, P>;
+  using Fr = typename Frag<P>::T;
+  constexpr int Q = L::Q;
+  __shared__ Fr wbk[BL::NF * 64];
+  __shared__ float lds[4 * BL::per_wave];
+
+  const int lane = threadIdx.x & 63, lg = lane >> 4, li = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+  // Block-shared transposed weight fragments for the backward contractions.
+  for (int e = threadIdx.x; e < BL::NF * 64; e += 256) {
+    const int f = e >> 6, l = e & 63, g = l >> 4, i = l & 15;
+    f4 v;
+    if (f < BL::NF3) {  // W3^T: row h = 16 ob + i, k = q = 16 qc + 4 g + r
+      const int ob = f / S::QB, qc = f % S::QB;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int q = 16 * qc + 4 * g + r, h = 16 * ob + i;
+        v[r] = q < Q ? theta[S::oW3 + q * H + h] : 0.f;
+      }
+    } else if (f < BL::NF3 + BL::NF2) {  // W2^T: row h = 16 ob + i, k = o = 16 c + 4 g + r
+      const int ff = f - BL::NF3, ob = ff / S::HB, c = ff % S::HB;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = theta[S::oW2 + (16 * c + 4 * g + r) * H + 16 * ob + i];
+    } else {  // W1^T: row k = 16 c + i (input index), k' = o = 16 ob + 4 g + r
+      const int ff = f - BL::NF3 - BL::NF2, c = ff / S::HB, ob = ff % S::HB;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int k = 16 * c + i, o = 16 * ob + 4 * g + r;
+        v[r] = k < Q ? theta[S::oW1 + o * Q + k] : 0.f;
+      }
+    }
+    wbk[e] = to_frag<P>(v);
+  }
+  __syncthreads();
+
+  float* X = lds + wave * BL::per_wave;  // [64][SX] network input x0
+  float* D = X + 64 * BL::SX;            // [64][SD] dy, then overwritten by dx
+  float* T = D + 64 * BL::SD;            // [H][ST] transpose scratch
+
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int lb = (nb % 8 == 0) ? (bid % 8) * (nb / 8) + bid / 8 : bid;
+  const int nw = nb * 4, wv = lb * 4 + wave;
+  const int per = (nitems + nw - 1) / nw;
+  const int it0 = wv * per, it1 = min(it0 + per, nitems);
+
+  Weights<P, S> W;
+  W.load(theta);
+  const Fr* W3T = wbk;
+  const Fr* W2T = wbk + BL::NF3 * 64;
+  const Fr* W1T = wbk + (BL::NF3 + BL::NF2) * 64;
+
+  f4 dW1[S::HB][S::KX], dW2[S::HB][S::HB], dW3[S::QB][S::HB], db2[S::HB];
+#pragma unroll
+  for (int a = 0; a < S::HB; ++a) {
+    db2[a] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < S::KX; ++c) dW1[a][c] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < S::HB; ++c) dW2[a][c] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll
+  for (int a = 0; a < S::QB; ++a)
+#pragma unroll
+    for (int c = 0; c < S::HB; ++c) dW3[a][c] = f4{0.f, 0.f, 0.f, 0.f};
+  float db3[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) db3[q] = 0.f;
+
+  auto locate = [&](int it, int& b, int& x, int& y, int& z) {
+    int row = it / nxc, xc = it - row * nxc;
+    x = xc * 64 + lane;
+    y = row % G.ny;
+    int t = row / G.ny;
+    z = t % G.nz;
+    b = t / G.nz;
+  };
+  auto load = [&](int it, float g[Q], float mu[Q]) {
+    int b, x, y, z;
+    locate(it, b, x, y, z);
+    if (x < G.nx) {
+      gather<L>(A, G, b, x, y, z, g);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) mu[q] = lam1[cell(G, b, q, Q, x, y, z)];
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) g[q] = mu[q] = 0.f;
+    }
+  };
+
+  float gc[Q], mc[Q];
+  if (it0 < it1) load(it0, gc, mc);
+  for (int it = it0; it < it1; ++it) {
+    float gn[Q], mn[Q];
+    if (it + 1 < it1) load(it + 1, gn, mn);
+    int b, x, y, z;
+    locate(it, b, x, y, z);
+    float F3[3] = {0.f, 0.f, 0.f};
+    if (Fc.kind != 0) body_force(Fc, G, x, y, z, F3);
+    float nu[Q], lam[Q];
+    collide_adjoint<L>(gc, mc, rho0, omega, F3, Fc.kind != 0, nu, lam);
+
+    // stage x0 and dy = k nu in node-major rows (zero padding)
+#pragma unroll
+    for (int c = 0; c < 4 * S::KX; ++c) {
+      f4 v;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int k = 4 * c + r;
+        v[r] = k < Q ? gc[k] : (k == Q ? 1.f : 0.f);
+      }
+      *reinterpret_cast<f4*>(X + lane * BL::SX + 4 * c) = v;
+    }
+#pragma unroll
+    for (int c = 0; c < 4 * S::QB; ++c) {
+      f4 v;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int q = 4 * c + r;
+        float d = q < Q ? knn * nu[q] : 0.f;
+        v[r] = d;
+        if (q < Q) db3[q] += d;
+      }
+      *reinterpret_cast<f4*>(D + lane * BL::SD + 4 * c) = v;
+    }
+    wave_lds_sync();
+
+#pragma unroll 1
+    for (int jg = 0; jg < 4; ++jg) {
+      const int nrow = 16 * jg + li;
+      // forward recompute
+      Fr xin[S::KX];
+#pragma unroll
+      for (int c = 0; c < S::KX; ++c)
+        xin[c] = to_frag<P>(*reinterpret_cast<const f4*>(X + nrow * BL::SX + 16 * c + 4 * lg));
+      f4 t1[S::HB], t2[S::HB];
+      Fr h1[S::HB], h2[S::HB];
+#pragma unroll
+      for (int ob = 0; ob < S::HB; ++ob) {
+        t1[ob] = tanh4<P>(mma_row<P, S::KX>(f4{0.f, 0.f, 0.f, 0.f}, W.w1[ob], xin));
+        h1[ob] = to_frag<P>(t1[ob]);
+      }
+#pragma unroll
+      for (int ob = 0; ob < S::HB; ++ob) {
+        t2[ob] = tanh4<P>(mma_row<P, S::HB>(W.b2[ob], W.w2[ob], h1));
+        h2[ob] = to_frag<P>(t2[ob]);
+      }
+      // dy in both operand layouts
+      Fr dyf[S::QB], dyT[S::QB];
+#pragma unroll
+      for (int qc = 0; qc < S::QB; ++qc) {
+        dyf[qc] = to_frag<P>(*reinterpret_cast<const f4*>(D + nrow * BL::SD + 16 * qc + 4 * lg));
+        f4 v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = D[(16 * jg + 4 * lg + r) * BL::SD + 16 * qc + li];
+        dyT[qc] = to_frag<P>(v);
+      }
+      // d2 = (W3^T dy) (1 - t2^2)
+      f4 d2[S::HB];
+      Fr d2f[S::HB];
+#pragma unroll
+      for (int ob = 0; ob < S::HB; ++ob) {
+        f4 a = mma_row_lds<P, S::QB>(f4{0.f, 0.f, 0.f, 0.f}, W3T + ob * S::QB * 64 + lane, dyf);
+        d2[ob] = a * (1.f - t2[ob] * t2[ob]);
+        db2[ob] += d2[ob];
+        d2f[ob] = to_frag<P>(d2[ob]);
+      }
+      // d1 = (W2^T d2) (1 - t1^2)
+      f4 d1[S::HB];
+      Fr d1f[S::HB];
+#pragma unroll
+      for (int ob = 0; ob < S::HB; ++ob) {
+        f4 a = mma_row_lds<P, S::HB>(f4{0.f, 0.f, 0.f, 0.f}, W2T + ob * S::HB * 64 + lane, d2f);
+        d1[ob] = a * (1.f - t1[ob] * t1[ob]);
+        d1f[ob] = to_frag<P>(d1[ob]);
+      }
+      // weight gradients, contraction over the 16 nodes of the group
+      {
+        Fr h2T[S::HB];
+#pragma unroll
+        for (int ib = 0; ib < S::HB; ++ib) {
+          h2T[ib] = to_frag<P>(transpose_chunk<BL::ST>(T, ib, t2[ib], lg, li));
+        }
+#pragma unroll
+        for (int qc = 0; qc < S::QB; ++qc)
+#pragma unroll
+          for (int ib = 0; ib < S::HB; ++ib) dW3[qc][ib] = mma_chunk<P>(dW3[qc][ib], dyT[qc], h2T[ib]);
+      }
+      wave_lds_sync();
+      {
+        Fr h1T[S::HB], d2T[S::HB];
+#pragma unroll
+        for (int ib = 0; ib < S::HB; ++ib) {
+          h1T[ib] = to_frag<P>(transpose_chunk<BL::ST>(T, ib, t1[ib], lg, li));
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int ob = 0; ob < S::HB; ++ob) d2T[ob] = to_frag<P>(transpose_chunk<BL::ST>(T, ob, d2[ob], lg, li));
+#pragma unroll
+        for (int ob = 0; ob < S::HB; ++ob)
+#pragma unroll
+          for (int ib = 0; ib < S::HB; ++ib) dW2[ob][ib] = mma_chunk<P>(dW2[ob][ib], d2T[ob], h1T[ib]);
+      }
+      wave_lds_sync();
+      {
+        Fr d1T[S::HB], x0T[S::KX];
+#pragma unroll
+        for (int ob = 0; ob < S::HB; ++ob) d1T[ob] = to_frag<P>(transpose_chunk<BL::ST>(T, ob, d1[ob], lg, li));
+#pragma unroll
+        for (int c = 0; c < S::KX; ++c) {
+          f4 v;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[r] = X[(16 * jg + 4 * lg + r) * BL::SX + 16 * c + li];
+          x0T[c] = to_frag<P>(v);
+        }
+#pragma unroll
+        for (int ob = 0; ob < S::HB; ++ob)
+#pragma unroll
+          for (int c = 0; c < S::KX; ++c) dW1[ob][c] = mma_chunk<P>(dW1[ob][c], d1T[ob], x0T[c]);
+      }
+      wave_lds_sync();
+      // dx = W1^T d1, over the input rows of this group (overwrites the
+      // group's own dy rows, which are no longer read)
+#pragma unroll
+      for (int c = 0; c < S::KX; ++c) {
+        f4 a = mma_row_lds<P, S::HB>(f4{0.f, 0.f, 0.f, 0.f}, W1T + c * S::HB * 64 + lane, d1f);
+        *reinterpret_cast<f4*>(D + nrow * BL::SD + 16 * c + 4 * lg) = a;
+      }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) lam[q] += D[lane * BL::SD + q];
+    if (x < G.nx) scatter<L>(lam0, G, b, x, y, z, lam);
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      gc[q] = gn[q];
+      mc[q] = mn[q];
+    }
+  }
+
+  // per-wave partials
+  float* pw = part + (size_t)wv * S::n;
+#pragma unroll
+  for (int ob = 0; ob < S::HB; ++ob) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = 16 * ob + 4 * lg + r;
+#pragma unroll
+      for (int c = 0; c < S::KX; ++c) {
+        const int k = 16 * c + li;
+        if (k < Q) pw[S::oW1 + o * Q + k] = dW1[ob][c][r];
+        else if (k == Q) pw[S::ob1 + o] = dW1[ob][c][r];
+      }
+#pragma unroll
+      for (int c = 0; c < S::HB; ++c) pw[S::oW2 + o * H + 16 * c + li] = dW2[ob][c][r];
+      float s = db2[ob][r];
+      s += __shfl_xor(s, 8);
+      s += __shfl_xor(s, 4);
+      s += __shfl_xor(s, 2);
+      s += __shfl_xor(s, 1);
+      if (li == 0) pw[S::ob2 + o] = s;
+    }
+  }
+#pragma unroll
+  for (int qc = 0; qc < S::QB; ++qc)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int q = 16 * qc + 4 * lg + r;
+#pragma unroll
+      for (int c = 0; c < S::HB; ++c)
+        if (q < Q) pw[S::oW3 + q * H + 16 * c + li] = dW3[qc][c][r];
+    }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    float s = db3[q];
+    s += __shfl_xor(s, 32);
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 8);
+    s += __shfl_xor(s, 4);
+    s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 1);
+    if (lane == 0) pw[S::ob3 + q] = s;
+  }
+}
+
+// dtheta[p] += sum over waves w (in order) of part[w][p]; float64 sum.
+__global__ __launch_bounds__(256) void grad_reduce_kernel(const float* __restrict__ part, int nw,
+                                                          int np, float* __restrict__ dtheta) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= np) return;
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += part[(size_t)w * np + p];
+  dtheta[p] += (float)s;
+}
+
+}  // namespace lbm

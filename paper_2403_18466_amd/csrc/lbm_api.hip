@@ -1,0 +1,527 @@
+// lbm_api.hip -- host implementation of the C ABI declared in include/lbm.h:
+// argument validation, dispatch to the kernel instances and launches on the
+// caller's stream.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "kernels_aux.hpp"
+#include "kernels_bwd.hpp"
+#include "kernels_fwd.hpp"
+#include "lbm.h"
+
+using namespace lbm;
+
+struct lbm_ctx {
+  lbm_config cfg;
+  int device;
+  int ncu;
+  double* partial;  // float64 reduction partials, [batch][MOM_BLOCKS][3]
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define LBM_HIP(expr)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) return fail(LBM_ERR_HIP, std::string(#expr) + ": " +      \
+                                                       hipGetErrorString(e_));      \
+  } while (0)
+
+#define LBM_LAUNCHED(name)                                                          \
+  do {                                                                              \
+    hipError_t e_ = hipGetLastError();                                              \
+    if (e_ != hipSuccess)                                                           \
+      return fail(LBM_ERR_HIP, std::string("launch of ") + name + ": " +            \
+                                   hipGetErrorString(e_));                          \
+  } while (0)
+
+int lattice_q(int lat) { return lat == LBM_D2Q9 ? 9 : 19; }
+int lattice_d(int lat) { return lat == LBM_D2Q9 ? 2 : 3; }
+
+Grid grid_of(const lbm_config& c) {
+  Grid G;
+  G.nx = c.nx;
+  G.ny = c.ny;
+  G.nz = c.nz;
+  G.batch = c.batch;
+  G.plane = c.nx * c.ny * c.nz;
+  return G;
+}
+
+Force force_of(const lbm_config& c) {
+  Force f;
+  f.kind = c.force_kind;
+  f.k = c.force_k;
+  f.amp = (float)c.force_amp;
+  return f;
+}
+
+size_t param_count(int lat, int H) {
+  if (H <= 0) return 0;
+  size_t Q = (size_t)lattice_q(lat), h = (size_t)H;
+  return h * Q + h + h * h + h + Q * h + Q;
+}
+
+lbm_status validate(const lbm_config* c) {
+  if (!c) return fail(LBM_ERR_INVALID, "config is null");
+  if (c->lattice != LBM_D2Q9 && c->lattice != LBM_D3Q19)
+    return fail(LBM_ERR_INVALID, "lattice must be LBM_D2Q9 or LBM_D3Q19");
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1 || c->batch < 1)
+    return fail(LBM_ERR_INVALID, "nx, ny, nz and batch must be >= 1");
+  if (c->lattice == LBM_D2Q9 && c->nz != 1) return fail(LBM_ERR_INVALID, "D2Q9 needs nz == 1");
+  double elems = (double)c->batch * lattice_q(c->lattice) * c->nx * (double)c->ny * c->nz;
+  if (elems >= 2147483648.0)
+    return fail(LBM_ERR_INVALID, "batch*Q*nx*ny*nz must stay below 2^31 elements");
+  if (!(c->tau > 0.5) || !std::isfinite(c->tau))
+    return fail(LBM_ERR_INVALID, "tau must be finite and > 0.5");
+  if (!(c->rho0 > 0.0) || !std::isfinite(c->rho0))
+    return fail(LBM_ERR_INVALID, "rho0 must be finite and > 0");
+  if (c->force_kind < LBM_FORCE_NONE || c->force_kind > LBM_FORCE_SINE3)
+    return fail(LBM_ERR_INVALID, "unknown force_kind");
+  if (c->force_kind == LBM_FORCE_SINE3 && c->lattice != LBM_D3Q19)
+    return fail(LBM_ERR_INVALID, "the three-component sine force needs D3Q19");
+  if (c->force_kind != LBM_FORCE_NONE && !std::isfinite(c->force_amp))
+    return fail(LBM_ERR_INVALID, "force_amp must be finite");
+  if (c->hidden != 0) {
+    if (c->hidden != 32 && c->hidden != 64)
+      return fail(LBM_ERR_UNSUPPORTED, "hidden must be 0, 32 or 64");
+    if (c->mlp_prec != LBM_MLP_FP32 && c->mlp_prec != LBM_MLP_BF16 &&
+        c->mlp_prec != LBM_MLP_FP16)
+      return fail(LBM_ERR_INVALID, "mlp_prec must be LBM_MLP_FP32, _BF16 or _FP16");
+    if (!std::isfinite(c->out_scale)) return fail(LBM_ERR_INVALID, "out_scale must be finite");
+  }
+  return LBM_OK;
+}
+
+lbm_status check_ctx(const lbm_ctx* ctx) {
+  if (!ctx) return fail(LBM_ERR_INVALID, "context is null");
+  int dev = -1;
+  LBM_HIP(hipGetDevice(&dev));
+  if (dev != ctx->device)
+    return fail(LBM_ERR_INVALID, "current device differs from the context's device");
+  return LBM_OK;
+}
+
+unsigned blocks_for(long long n, int per_block = 256) {
+  return (unsigned)((n + per_block - 1) / per_block);
+}
+
+// ------------------------------------------------------------------ forward
+template <class L>
+lbm_status run_init(lbm_ctx* ctx, const float* rho, const float* u, float* A, hipStream_t s) {
+  Grid G = grid_of(ctx->cfg);
+  long long total = (long long)G.plane * G.batch;
+  hipLaunchKernelGGL(init_kernel<L>, dim3(blocks_for(total)), dim3(256), 0, s, rho, u, A, G,
+                     (float)ctx->cfg.rho0);
+  LBM_LAUNCHED("init_kernel");
+  return LBM_OK;
+}
+
+template <class L>
+lbm_status run_shift(lbm_ctx* ctx, const float* src, float* dst, int dir, hipStream_t s) {
+  Grid G = grid_of(ctx->cfg);
+  long long total = (long long)G.plane * G.batch;
+  hipLaunchKernelGGL(shift_kernel<L>, dim3(blocks_for(total)), dim3(256), 0, s, src, dst, G,
+                     dir);
+  LBM_LAUNCHED("shift_kernel");
+  return LBM_OK;
+}
+
+template <class L>
+lbm_status run_moments(lbm_ctx* ctx, const float* A, float* rho, float* u, double* diag,
+                       hipStream_t s) {
+  Grid G = grid_of(ctx->cfg);
+  hipLaunchKernelGGL(moments_kernel<L>, dim3(MOM_BLOCKS, G.batch), dim3(256), 0, s, A, rho, u,
+                     ctx->partial, G, (float)ctx->cfg.rho0, force_of(ctx->cfg));
+  LBM_LAUNCHED("moments_kernel");
+  if (diag) {
+    hipLaunchKernelGGL(diag_reduce_kernel, dim3(G.batch), dim3(256), 0, s, ctx->partial, diag,
+                       MOM_BLOCKS);
+    LBM_LAUNCHED("diag_reduce_kernel");
+  }
+  return LBM_OK;
+}
+
+template <class L>
+lbm_status launch_bgk(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t s) {
+  Grid G = grid_of(ctx->cfg);
+  int nxc = (G.nx + 255) / 256;
+  long long nblk = (long long)nxc * G.ny * G.nz * G.batch;
+  hipLaunchKernelGGL(bgk_step_kernel<L>, dim3((unsigned)nblk), dim3(256), 0, s, Ain, Aout, G,
+                     force_of(ctx->cfg), (float)ctx->cfg.rho0, (float)(1.0 / ctx->cfg.tau),
+                     nxc);
+  LBM_LAUNCHED("bgk_step_kernel");
+  return LBM_OK;
+}
+
+// Workgroups for a persistent kernel: as many as fit on the chip at once,
+// no more than there are work units, a multiple of the 8 XCDs when large.
+template <class K>
+lbm_status persistent_blocks(lbm_ctx* ctx, K kernel, long long units_per_block_min,
+                             long long units, unsigned& blocks) {
+  int occ = 0;
+  LBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 256, 0));
+  if (occ < 1) occ = 1;
+  long long want = (long long)ctx->ncu * occ;
+  long long cap = (units + units_per_block_min - 1) / units_per_block_min;
+  long long nb = want < cap ? want : cap;
+  if (nb >= 16) nb -= nb % 8;
+  if (nb < 1) nb = 1;
+  blocks = (unsigned)nb;
+  return LBM_OK;
+}
+
+template <class L, int H, int P>
+lbm_status launch_nlbm(lbm_ctx* ctx, const float* Ain, float* Aout, const float* theta,
+                       hipStream_t s) {
+  Grid G = grid_of(ctx->cfg);
+  int nxc = (G.nx + 63) / 64;
+  long long nitems = (long long)nxc * G.ny * G.nz * G.batch;
+  if (nitems >= (1LL << 31)) return fail(LBM_ERR_INVALID, "too many work items");
+  unsigned blocks = 0;
+  lbm_status st = persistent_blocks(ctx, nlbm_step_kernel<L, H, P>, 4, nitems, blocks);
+  if (st != LBM_OK) return st;
+  const lbm_config& c = ctx->cfg;
+  hipLaunchKernelGGL((nlbm_step_kernel<L, H, P>), dim3(blocks), dim3(256), 0, s, Ain, Aout,
+                     theta, G, force_of(c), (float)c.rho0, (float)(1.0 / c.tau),
+                     (float)(c.out_scale / c.tau), (int)nitems, nxc);
+  LBM_LAUNCHED("nlbm_step_kernel");
+  return LBM_OK;
+}
+
+template <class L, int H>
+lbm_status launch_nlbm_p(lbm_ctx* ctx, const float* Ain, float* Aout, const float* theta,
+                         hipStream_t s) {
+  switch (ctx->cfg.mlp_prec) {
+    case LBM_MLP_FP32: return launch_nlbm<L, H, P_F32>(ctx, Ain, Aout, theta, s);
+    case LBM_MLP_BF16: return launch_nlbm<L, H, P_BF16>(ctx, Ain, Aout, theta, s);
+    default: return launch_nlbm<L, H, P_F16>(ctx, Ain, Aout, theta, s);
+  }
+}
+
+template <class L>
+lbm_status one_step(lbm_ctx* ctx, const float* Ain, float* Aout, const float* theta,
+                    hipStream_t s) {
+  switch (ctx->cfg.hidden) {
+    case 0: return launch_bgk<L>(ctx, Ain, Aout, s);
+    case 32: return launch_nlbm_p<L, 32>(ctx, Ain, Aout, theta, s);
+    default: return launch_nlbm_p<L, 64>(ctx, Ain, Aout, theta, s);
+  }
+}
+
+// ----------------------------------------------------------------- backward
+template <class L, int H, int P>
+lbm_status launch_bwd(lbm_ctx* ctx, const float* A, const float* theta, const float* lam1,
+                      float* lam0, float* dtheta, void* ws, hipStream_t s) {
+  Grid G = grid_of(ctx->cfg);
+  int nxc = (G.nx + 63) / 64;
+  long long nitems = (long long)nxc * G.ny * G.nz * G.batch;
+  if (nitems >= (1LL << 31)) return fail(LBM_ERR_INVALID, "too many work items");
+  const lbm_config& c = ctx->cfg;
+  const int nparam = (int)param_count(c.lattice, c.hidden);
+  float* part = static_cast<float*>(ws);
+  const unsigned blocks = bwd_blocks(ctx->ncu);
+  hipLaunchKernelGGL((nlbm_backward_kernel<L, H, P>), dim3(blocks), dim3(256), 0, s, A, theta,
+                     lam1, lam0, part, G, force_of(c), (float)c.rho0, (float)(1.0 / c.tau),
+                     (float)(c.out_scale / c.tau), (int)nitems, nxc);
+  LBM_LAUNCHED("nlbm_backward_kernel");
+  hipLaunchKernelGGL(grad_reduce_kernel, dim3(blocks_for(nparam)), dim3(256), 0, s, part,
+                     (int)(blocks * 4), nparam, dtheta);
+  LBM_LAUNCHED("grad_reduce_kernel");
+  return LBM_OK;
+}
+
+template <class L, int H>
+lbm_status launch_bwd_p(lbm_ctx* ctx, const float* A, const float* theta, const float* lam1,
+                        float* lam0, float* dtheta, void* ws, hipStream_t s) {
+  switch (ctx->cfg.mlp_prec) {
+    case LBM_MLP_FP32: return launch_bwd<L, H, P_F32>(ctx, A, theta, lam1, lam0, dtheta, ws, s);
+    case LBM_MLP_BF16: return launch_bwd<L, H, P_BF16>(ctx, A, theta, lam1, lam0, dtheta, ws, s);
+    default: return launch_bwd<L, H, P_F16>(ctx, A, theta, lam1, lam0, dtheta, ws, s);
+  }
+}
+
+template <class L>
+lbm_status run_backward(lbm_ctx* ctx, const float* A, const float* theta, const float* lam1,
+                        float* lam0, float* dtheta, void* ws, hipStream_t s) {
+  const lbm_config& c = ctx->cfg;
+  if (c.hidden == 0) {
+    Grid G = grid_of(c);
+    int nxc = (G.nx + 255) / 256;
+    long long nblk = (long long)nxc * G.ny * G.nz * G.batch;
+    hipLaunchKernelGGL(bgk_backward_kernel<L>, dim3((unsigned)nblk), dim3(256), 0, s, A, lam1,
+                       lam0, G, force_of(c), (float)c.rho0, (float)(1.0 / c.tau), nxc);
+    LBM_LAUNCHED("bgk_backward_kernel");
+    return LBM_OK;
+  }
+  if (c.hidden == 32) return launch_bwd_p<L, 32>(ctx, A, theta, lam1, lam0, dtheta, ws, s);
+  return launch_bwd_p<L, 64>(ctx, A, theta, lam1, lam0, dtheta, ws, s);
+}
+
+template <class L>
+lbm_status run_loss(lbm_ctx* ctx, const float* A, const float* ut, double* loss, float* dLdA,
+                    hipStream_t s) {
+  Grid G = grid_of(ctx->cfg);
+  const int nblk = MOM_BLOCKS;
+  double count = (double)G.plane * G.batch * L::D;
+  hipLaunchKernelGGL(loss_kernel<L>, dim3(nblk), dim3(256), 0, s, A, ut, dLdA, ctx->partial, G,
+                     (float)ctx->cfg.rho0, force_of(ctx->cfg), 1.0 / count);
+  LBM_LAUNCHED("loss_kernel");
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, ctx->partial, nblk,
+                     1.0 / count, loss);
+  LBM_LAUNCHED("sum_partials_kernel");
+  return LBM_OK;
+}
+
+}  // namespace
+
+#define LBM_GUARD_BEGIN try {
+#define LBM_GUARD_END                                                        \
+  }                                                                          \
+  catch (const std::exception& e) {                                          \
+    return fail(LBM_ERR_HIP, std::string("internal error: ") + e.what());    \
+  }                                                                          \
+  catch (...) {                                                              \
+    return fail(LBM_ERR_HIP, "internal error");                              \
+  }
+
+extern "C" {
+
+lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
+  LBM_GUARD_BEGIN
+  if (!out) return fail(LBM_ERR_INVALID, "out is null");
+  *out = nullptr;
+  lbm_status st = validate(cfg);
+  if (st != LBM_OK) return st;
+  int dev = 0;
+  LBM_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  LBM_HIP(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(LBM_ERR_UNSUPPORTED, std::string("built for gfx950, device is ") +
+                                         prop.gcnArchName);
+  lbm_ctx* ctx = new (std::nothrow) lbm_ctx;
+  if (!ctx) return fail(LBM_ERR_INVALID, "out of host memory");
+  ctx->cfg = *cfg;
+  ctx->device = dev;
+  ctx->ncu = prop.multiProcessorCount;
+  ctx->partial = nullptr;
+  size_t bytes = sizeof(double) * 3 * MOM_BLOCKS * (size_t)cfg->batch;
+  hipError_t e = hipMalloc(&ctx->partial, bytes);
+  if (e != hipSuccess) {
+    delete ctx;
+    return fail(LBM_ERR_HIP, std::string("hipMalloc of the reduction buffer: ") +
+                                 hipGetErrorString(e));
+  }
+  *out = ctx;
+  return LBM_OK;
+  LBM_GUARD_END
+}
+
+lbm_status lbm_destroy(lbm_ctx* ctx) {
+  LBM_GUARD_BEGIN
+  if (!ctx) return LBM_OK;
+  if (ctx->partial) (void)hipFree(ctx->partial);
+  delete ctx;
+  return LBM_OK;
+  LBM_GUARD_END
+}
+
+size_t lbm_state_elems(const lbm_ctx* ctx) {
+  if (!ctx) return 0;
+  const lbm_config& c = ctx->cfg;
+  return (size_t)c.batch * lattice_q(c.lattice) * c.nx * (size_t)c.ny * c.nz;
+}
+
+size_t lbm_param_elems(const lbm_ctx* ctx) {
+  if (!ctx) return 0;
+  return param_count(ctx->cfg.lattice, ctx->cfg.hidden);
+}
+
+size_t lbm_workspace_bytes(const lbm_ctx* ctx) {
+  if (!ctx || ctx->cfg.hidden == 0) return 0;
+  return sizeof(float) * (size_t)bwd_blocks(ctx->ncu) * 4 *
+         param_count(ctx->cfg.lattice, ctx->cfg.hidden);
+}
+
+lbm_status lbm_lattice_tables(int32_t lattice, int32_t* q, int32_t* c, double* w) {
+  LBM_GUARD_BEGIN
+  if (!q || !c || !w) return fail(LBM_ERR_INVALID, "null output pointer");
+  if (lattice == LBM_D2Q9) {
+    *q = D2Q9::Q;
+    for (int i = 0; i < D2Q9::Q; ++i) {
+      c[3 * i] = D2Q9::cx[i];
+      c[3 * i + 1] = D2Q9::cy[i];
+      c[3 * i + 2] = D2Q9::cz[i];
+      w[i] = D2Q9::wd[i];
+    }
+    return LBM_OK;
+  }
+  if (lattice == LBM_D3Q19) {
+    *q = D3Q19::Q;
+    for (int i = 0; i < D3Q19::Q; ++i) {
+      c[3 * i] = D3Q19::cx[i];
+      c[3 * i + 1] = D3Q19::cy[i];
+      c[3 * i + 2] = D3Q19::cz[i];
+      w[i] = D3Q19::wd[i];
+    }
+    return LBM_OK;
+  }
+  return fail(LBM_ERR_INVALID, "unknown lattice");
+  LBM_GUARD_END
+}
+
+lbm_status lbm_init(lbm_ctx* ctx, const float* rho, const float* u, float* A0,
+                    hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  lbm_status st = check_ctx(ctx);
+  if (st != LBM_OK) return st;
+  if (!rho || !u || !A0) return fail(LBM_ERR_INVALID, "null array");
+  if (ctx->cfg.lattice == LBM_D2Q9) return run_init<D2Q9>(ctx, rho, u, A0, stream);
+  return run_init<D3Q19>(ctx, rho, u, A0, stream);
+  LBM_GUARD_END
+}
+
+lbm_status lbm_step(lbm_ctx* ctx, float* A, float* B, const float* theta, int32_t nsteps,
+                    hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  lbm_status st = check_ctx(ctx);
+  if (st != LBM_OK) return st;
+  if (!A || !B) return fail(LBM_ERR_INVALID, "null state buffer");
+  if (A == B) return fail(LBM_ERR_INVALID, "A and B must be different buffers");
+  if (nsteps < 1) return fail(LBM_ERR_INVALID, "nsteps must be >= 1");
+  if (ctx->cfg.hidden != 0 && !theta) return fail(LBM_ERR_INVALID, "theta is null");
+  float* buf[2] = {A, B};
+  for (int s = 0; s < nsteps; ++s) {
+    const float* in = buf[s & 1];
+    float* out = buf[(s + 1) & 1];
+    st = ctx->cfg.lattice == LBM_D2Q9 ? one_step<D2Q9>(ctx, in, out, theta, stream)
+                                      : one_step<D3Q19>(ctx, in, out, theta, stream);
+    if (st != LBM_OK) return st;
+  }
+  return LBM_OK;
+  LBM_GUARD_END
+}
+
+lbm_status lbm_moments(lbm_ctx* ctx, const float* A, float* rho, float* u, double* diag,
+                       hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  lbm_status st = check_ctx(ctx);
+  if (st != LBM_OK) return st;
+  if (!A) return fail(LBM_ERR_INVALID, "null state");
+  if (ctx->cfg.lattice == LBM_D2Q9) return run_moments<D2Q9>(ctx, A, rho, u, diag, stream);
+  return run_moments<D3Q19>(ctx, A, rho, u, diag, stream);
+  LBM_GUARD_END
+}
+
+lbm_status lbm_shift(lbm_ctx* ctx, const float* src, float* dst, int32_t direction,
+                     hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  lbm_status st = check_ctx(ctx);
+  if (st != LBM_OK) return st;
+  if (!src || !dst) return fail(LBM_ERR_INVALID, "null array");
+  if (src == dst) return fail(LBM_ERR_INVALID, "src and dst must differ");
+  if (direction != 1 && direction != -1) return fail(LBM_ERR_INVALID, "direction must be +1 or -1");
+  if (ctx->cfg.lattice == LBM_D2Q9) return run_shift<D2Q9>(ctx, src, dst, direction, stream);
+  return run_shift<D3Q19>(ctx, src, dst, direction, stream);
+  LBM_GUARD_END
+}
+
+lbm_status lbm_step_backward(lbm_ctx* ctx, const float* A_n, const float* theta,
+                             const float* lam_n1, float* lam_n, float* dtheta, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  lbm_status st = check_ctx(ctx);
+  if (st != LBM_OK) return st;
+  if (!A_n || !lam_n1 || !lam_n) return fail(LBM_ERR_INVALID, "null array");
+  if (lam_n == lam_n1 || lam_n == A_n)
+    return fail(LBM_ERR_INVALID, "lam_n must not alias lam_n1 or A_n");
+  if (ctx->cfg.hidden != 0) {
+    if (!theta || !dtheta) return fail(LBM_ERR_INVALID, "theta and dtheta must be given");
+    if (!ws) return fail(LBM_ERR_INVALID, "workspace is null");
+    if (ws_bytes < lbm_workspace_bytes(ctx))
+      return fail(LBM_ERR_WORKSPACE, "workspace smaller than lbm_workspace_bytes()");
+  }
+  if (ctx->cfg.lattice == LBM_D2Q9)
+    return run_backward<D2Q9>(ctx, A_n, theta, lam_n1, lam_n, dtheta, ws, stream);
+  return run_backward<D3Q19>(ctx, A_n, theta, lam_n1, lam_n, dtheta, ws, stream);
+  LBM_GUARD_END
+}
+
+lbm_status lbm_loss_velocity_mse(lbm_ctx* ctx, const float* A, const float* u_target,
+                                 double* loss, float* dLdA, hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  lbm_status st = check_ctx(ctx);
+  if (st != LBM_OK) return st;
+  if (!A || !u_target || !loss) return fail(LBM_ERR_INVALID, "null array");
+  if (dLdA == A) return fail(LBM_ERR_INVALID, "dLdA must not alias A");
+  if (ctx->cfg.lattice == LBM_D2Q9) return run_loss<D2Q9>(ctx, A, u_target, loss, dLdA, stream);
+  return run_loss<D3Q19>(ctx, A, u_target, loss, dLdA, stream);
+  LBM_GUARD_END
+}
+
+lbm_status lbm_adam(float* param, const float* grad, float* m, float* v, int64_t n, double lr,
+                    double beta1, double beta2, double eps, double weight_decay, int32_t t,
+                    hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  if (!param || !grad || !m || !v) return fail(LBM_ERR_INVALID, "null array");
+  if (n < 0) return fail(LBM_ERR_INVALID, "n must be >= 0");
+  if (t < 1) return fail(LBM_ERR_INVALID, "t must be >= 1");
+  if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+    return fail(LBM_ERR_INVALID, "betas must lie in [0, 1)");
+  if (n == 0) return LBM_OK;
+  float bc1 = (float)(1.0 - std::pow(beta1, t)), bc2 = (float)(1.0 - std::pow(beta2, t));
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, param, grad, m, v,
+                     (long long)n, (float)lr, (float)beta1, (float)beta2, (float)eps,
+                     (float)weight_decay, bc1, bc2);
+  LBM_LAUNCHED("adam_kernel");
+  return LBM_OK;
+  LBM_GUARD_END
+}
+
+lbm_status lbm_box_filter(const float* src, float* dst, int32_t batch, int32_t channels,
+                          int32_t nx, int32_t ny, int32_t nz, int32_t factor,
+                          hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  if (!src || !dst) return fail(LBM_ERR_INVALID, "null array");
+  if (src == dst) return fail(LBM_ERR_INVALID, "src and dst must differ");
+  if (batch < 1 || channels < 1 || nx < 1 || ny < 1 || nz < 1 || factor < 1)
+    return fail(LBM_ERR_INVALID, "sizes must be >= 1");
+  int fz = nz > 1 ? factor : 1;
+  if (nx % factor || ny % factor || nz % fz)
+    return fail(LBM_ERR_INVALID, "grid sizes must be multiples of factor");
+  long long total = (long long)batch * channels * (nz / fz) * (ny / factor) * (nx / factor);
+  hipLaunchKernelGGL(box_filter_kernel, dim3(blocks_for(total)), dim3(256), 0, stream, src, dst,
+                     batch, channels, nx, ny, nz, factor, fz);
+  LBM_LAUNCHED("box_filter_kernel");
+  return LBM_OK;
+  LBM_GUARD_END
+}
+
+const char* lbm_status_str(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "LBM_OK";
+    case LBM_ERR_INVALID: return "LBM_ERR_INVALID";
+    case LBM_ERR_UNSUPPORTED: return "LBM_ERR_UNSUPPORTED";
+    case LBM_ERR_HIP: return "LBM_ERR_HIP";
+    case LBM_ERR_WORKSPACE: return "LBM_ERR_WORKSPACE";
+  }
+  return "unknown status";
+}
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
