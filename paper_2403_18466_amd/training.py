@@ -1,0 +1,100 @@
+"""Differentiable time stepping and unrolled training of the collision network
+(SI, "Unrolled training": roll the model over L_T steps, evaluate the loss at
+the end, backpropagate through every step, update with Adam).
+
+Everything here orchestrates library calls; the arithmetic (steps, adjoint
+steps, loss and its gradient, Adam, coarse-graining) runs in liblbm_hip.so.
+PyTorch provides device memory, streams and the autograd interface.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import lbm
+
+
+class NLBMStep(torch.autograd.Function):
+    """One stream-collide step A_{n+1} = step(A_n; theta) with the hand-written
+    adjoint as its backward.  Usage: NLBMStep.apply(lattice, A, theta)."""
+
+    @staticmethod
+    def forward(ctx, lattice: "lbm.Lattice", A, theta):
+        ctx.lattice = lattice
+        ctx.save_for_backward(A, theta)
+        out = lattice.empty_state()
+        # a single step reads A and writes out; A is left untouched
+        return lbm.lbm_step(lattice.ctx, lattice.cfg, A.detach(), out, theta.detach(), 1)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        A, theta = ctx.saved_tensors
+        L = ctx.lattice
+        lam_n, dtheta = L.step_backward(A.detach(), theta.detach(),
+                                        grad_out.contiguous())
+        return None, lam_n, dtheta
+
+
+def unrolled_loss_and_grad(L: "lbm.Lattice", A0, theta, u_target, nsteps: int, ckpt: int = 8,
+                           want_dA0: bool = False):
+    """Velocity-MSE loss after `nsteps` steps from A0 and its gradient.
+
+    Forward keeps the state at every multiple of `ckpt` (plus A0); the
+    backward pass walks the segments in reverse, recomputes each segment's
+    states from its checkpoint, and applies lbm_step_backward step by step.
+    Memory: nsteps/ckpt checkpoints + ckpt segment states + 2 adjoint buffers.
+    Returns (loss [1] float64 device tensor, dtheta, dA0 or None)."""
+    assert nsteps >= 1 and ckpt >= 1
+    ckpts = {0: A0}
+    a = A0.detach().clone()
+    b = L.empty_state()
+    for n in range(nsteps):
+        res = lbm.lbm_step(L.ctx, L.cfg, a, b, theta, 1)
+        a, b = res, (a if res is b else b)
+        if (n + 1) % ckpt == 0 and n + 1 < nsteps:
+            ckpts[n + 1] = a.clone()
+    loss, lam = L.loss_velocity_mse(a, u_target, want_grad=True)
+    dtheta = torch.zeros(L.n_param, dtype=torch.float32, device=L.device)
+    lam_next = torch.empty_like(lam)
+    ws = L.workspace()
+    n = nsteps
+    while n > 0:
+        start = ((n - 1) // ckpt) * ckpt
+        seg = [ckpts[start]]
+        for m in range(start, n - 1):
+            out = L.empty_state()
+            lbm.lbm_step(L.ctx, L.cfg, seg[-1], out, theta, 1)
+            seg.append(out)
+        for m in range(n - 1, start - 1, -1):
+            lbm.lbm_step_backward(L.ctx, L.cfg, seg[m - start], theta, lam, lam_next, dtheta, ws)
+            lam, lam_next = lam_next, lam
+        n = start
+    return loss, dtheta, (lam if want_dA0 else None)
+
+
+class Adam:
+    """Adam with L2 weight decay added to the gradient (Table S2 of the SI:
+    learning rate 1e-4, weight decay 1e-6), on the library's adam kernel."""
+
+    def __init__(self, param, lr=1e-4, betas=(0.9, 0.999), eps=1e-8, weight_decay=1e-6):
+        self.p = param
+        self.m = torch.zeros_like(param)
+        self.v = torch.zeros_like(param)
+        self.lr, self.betas, self.eps, self.wd = lr, betas, eps, weight_decay
+        self.t = 0
+
+    def step(self, grad):
+        self.t += 1
+        lbm.lbm_adam(self.p, grad, self.m, self.v, self.lr, self.betas[0], self.betas[1],
+                     self.eps, self.wd, self.t)
+
+
+def coarse_grain(fine: "lbm.Lattice", coarse: "lbm.Lattice", A_fine, factor: int):
+    """Block-average the fine populations onto the coarse grid (4 x 4 blocks for
+    factor 4): canonical fine -> box filter -> pull-shifted coarse.  The
+    coarse velocity (j summed over the block over rho summed over the block)
+    is then the coarse state's own moment."""
+    cf = fine.cfg
+    canon = fine.shift(A_fine, +1)
+    cc = coarse.empty_state()
+    lbm.lbm_box_filter(canon, cc, cf.batch, cf.Q, cf.nx, cf.ny, cf.nz, factor)
+    return coarse.shift(cc, -1)

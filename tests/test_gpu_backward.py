@@ -1,0 +1,185 @@
+"""GPU parity of the adjoint path (lbm_step_backward, the velocity-MSE loss
+and its gradient, Adam, the box filter, the checkpointed unrolled gradient)
+against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from lbm_cases import lib_config, params, random_state, rel_l2, to_canonical, to_shifted
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_18466_amd import lbm as m
+    m.load_library()
+    return m
+
+
+def dev(a, dtype=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def gpu_adjoint(lbm, ocfg, g, lam1, theta, prec="fp32"):
+    L = lbm.Lattice(lib_config(ocfg, prec))
+    th = dev(theta) if theta is not None else None
+    lam0, dth = L.step_backward(dev(to_shifted(g, ocfg.lattice)), th,
+                                dev(to_shifted(lam1, ocfg.lattice)))
+    out = to_canonical(host(lam0), ocfg.lattice), (host(dth) if dth is not None else None)
+    L.close()
+    return out
+
+
+@pytest.mark.parametrize("lat,shape,force", [("D2Q9", (1, 9, 70), 0), ("D2Q9", (1, 16, 16), 1),
+                                             ("D3Q19", (5, 6, 7), 0), ("D3Q19", (6, 6, 6), 2)])
+def test_bgk_adjoint_parity(lbm, lat, shape, force):
+    nz, ny, nx = shape
+    kw = {1: dict(force_kind=1, force_amp=1e-3, force_k=1),
+          2: dict(force_kind=2, force_amp=1e-3, force_k=1)}.get(force, {})
+    ocfg = oracle.Config(lattice=lat, nx=nx, ny=ny, nz=nz, batch=2, tau=0.55, **kw)
+    g = random_state(ocfg, 11, scale=0.03)
+    lam1 = random_state(ocfg, 12, scale=1.0)
+    want, _ = oracle.step_adjoint(ocfg, g, lam1)
+    got, _ = gpu_adjoint(lbm, ocfg, g, lam1, None)
+    assert rel_l2(got, want) < 2e-6
+
+
+@pytest.mark.parametrize("lat,shape,H,force", [
+    ("D2Q9", (1, 8, 8), 32, 0),
+    ("D2Q9", (1, 12, 70), 64, 0),
+    ("D2Q9", (1, 16, 33), 64, 1),
+    ("D3Q19", (4, 5, 70), 64, 0),
+    ("D3Q19", (5, 5, 5), 32, 2),
+])
+def test_nlbm_adjoint_fp32_parity(lbm, lat, shape, H, force):
+    nz, ny, nx = shape
+    kw = {1: dict(force_kind=1, force_amp=1e-3, force_k=1),
+          2: dict(force_kind=2, force_amp=1e-3, force_k=1)}.get(force, {})
+    ocfg = oracle.Config(lattice=lat, nx=nx, ny=ny, nz=nz, batch=2, tau=0.55, hidden=H,
+                         out_scale=0.25, **kw)
+    theta = params(ocfg.Q, H, seed=13, kind="random")
+    g = random_state(ocfg, 14, scale=0.03)
+    lam1 = random_state(ocfg, 15, scale=1.0)
+    want, wdth = oracle.step_adjoint(ocfg, g, lam1, theta.astype(np.float64))
+    got, gdth = gpu_adjoint(lbm, ocfg, g, lam1, theta)
+    e_lam, e_th = rel_l2(got, want), rel_l2(gdth, wdth)
+    print(f"{lat} H={H}: lam rel L2 {e_lam:.2e}, dtheta rel L2 {e_th:.2e}")
+    assert e_lam < 1e-5
+    assert e_th < 1e-5
+    # every block of the packed gradient is nonzero and matches on its own
+    Q = ocfg.Q
+    offs = [0, H * Q, H * Q + H, H * Q + H + H * H, H * Q + 2 * H + H * H,
+            H * Q + 2 * H + H * H + Q * H, gdth.size]
+    for a, b in zip(offs[:-1], offs[1:]):
+        assert np.abs(wdth[a:b]).max() > 0
+        assert rel_l2(gdth[a:b], wdth[a:b]) < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_nlbm_adjoint_reduced_precision(lbm, prec):
+    """bf16/fp16 backward against the oracle's emulated-rounding adjoint (the
+    rounding is passed straight through the derivative).  The GPU also rounds
+    the backward operands (dy, d2, d1), so the bound is stated, not tight."""
+    ocfg = oracle.Config(nx=40, ny=24, batch=2, tau=0.51, hidden=64, out_scale=0.25, quant=prec)
+    theta = params(9, 64, seed=16)
+    g = random_state(ocfg, 17, scale=0.03)
+    lam1 = random_state(ocfg, 18, scale=1.0)
+    want, wdth = oracle.step_adjoint(ocfg, g, lam1, theta.astype(np.float64))
+    got, gdth = gpu_adjoint(lbm, ocfg, g, lam1, theta, prec=prec)
+    e_lam, e_th = rel_l2(got, want), rel_l2(gdth, wdth)
+    print(f"{prec}: lam rel L2 {e_lam:.2e}, dtheta rel L2 {e_th:.2e}")
+    assert e_lam < (2e-3 if prec == "bf16" else 3e-4)
+    assert e_th < (2e-2 if prec == "bf16" else 3e-3)
+
+
+@pytest.mark.parametrize("lat,shape,force", [("D2Q9", (1, 17, 70), 0), ("D2Q9", (1, 16, 8), 1),
+                                             ("D3Q19", (5, 6, 7), 0)])
+def test_loss_and_gradient(lbm, lat, shape, force):
+    nz, ny, nx = shape
+    kw = dict(force_kind=1, force_amp=1e-3, force_k=1) if force else {}
+    ocfg = oracle.Config(lattice=lat, nx=nx, ny=ny, nz=nz, batch=3, **kw)
+    g = random_state(ocfg, 19, scale=0.03)
+    ut = np.random.default_rng(20).uniform(-0.05, 0.05, (3, ocfg.D, nz, ny, nx))
+    ut = ut.astype(np.float32).astype(np.float64)
+    want_l, want_g = oracle.loss_velocity_mse(ocfg, g, ut)
+    L = lbm.Lattice(lib_config(ocfg))
+    loss, grad = L.loss_velocity_mse(dev(to_shifted(g, lat)), dev(ut))
+    assert abs(host(loss)[0] - want_l) < 1e-6 * want_l
+    assert rel_l2(to_canonical(host(grad), lat), want_g) < 1e-6
+
+
+def test_adam_matches_formula(lbm):
+    rng = np.random.default_rng(21)
+    n = 5385
+    p = rng.normal(size=n).astype(np.float32)
+    grads = [rng.normal(size=n).astype(np.float32) for _ in range(3)]
+    P, M, V = dev(p), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    lr, b1, b2, eps, wd = 1e-3, 0.9, 0.999, 1e-8, 1e-2
+    pp, m, v = p.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t, gr in enumerate(grads, start=1):
+        lbm.lbm_adam(P, dev(gr), M, V, lr, b1, b2, eps, wd, t)
+        gg = gr + wd * pp
+        m = b1 * m + (1 - b1) * gg
+        v = b2 * v + (1 - b2) * gg * gg
+        pp = pp - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+    assert np.abs(host(P) - pp).max() < 1e-5
+
+
+@pytest.mark.parametrize("nz", [1, 4])
+def test_box_filter(lbm, nz):
+    rng = np.random.default_rng(22)
+    b, c, ny, nx, f = 2, 3, 8, 12, 4
+    x = rng.normal(size=(b, c, nz, ny, nx)).astype(np.float32)
+    fz = f if nz > 1 else 1
+    out = torch.empty((b, c, nz // fz, ny // f, nx // f), device="cuda")
+    lbm.lbm_box_filter(dev(x), out, b, c, nx, ny, nz, f)
+    want = x.astype(np.float64).reshape(b, c, nz // fz, fz, ny // f, f, nx // f, f).mean(axis=(3, 5, 7))
+    assert np.abs(host(out) - want).max() < 1e-6
+
+
+def test_unrolled_gradient_matches_oracle(lbm):
+    """32x32, 16 unrolled steps, checkpoint every 8, velocity-MSE loss: the
+    GPU fp32 gradient against the oracle's (relative L2 <= 1e-4)."""
+    from paper_2403_18466_amd import inputs, training
+    n, H, T = 32, 64, 16
+    ocfg = oracle.Config(nx=n, ny=n, tau=0.50125, hidden=H, out_scale=2.0 ** -4)
+    theta = params(9, H, seed=1)
+    theta[H * 9:H * 9 + H] = np.random.default_rng(20).uniform(-0.1, 0.1, H).astype(np.float32)
+    u0 = inputs.fourier_modes_velocity(n, n, kmax=4, umax=0.05, seed=0)
+    g0 = oracle.init_equilibrium(ocfg, np.ones((1, 1, n, n)), u0[None, :, None])
+    g0 = g0.astype(np.float32).astype(np.float64)
+    ut = (0.9 * inputs.fourier_modes_velocity(n, n, kmax=2, umax=0.04, seed=21)[None, :, None])
+    ut = ut.astype(np.float32).astype(np.float64)
+    wl, wdth, wlam = oracle.unrolled_loss_and_grad(ocfg, g0, theta.astype(np.float64), ut, T, ckpt=8)
+    L = lbm.Lattice(lib_config(ocfg))
+    loss, dth, dA0 = training.unrolled_loss_and_grad(L, dev(to_shifted(g0, "D2Q9")), dev(theta),
+                                                     dev(ut), T, ckpt=8, want_dA0=True)
+    assert abs(host(loss)[0] - wl) < 1e-5 * wl
+    e = rel_l2(host(dth), wdth)
+    print(f"unrolled gradient rel L2 {e:.2e}")
+    assert e < 1e-4
+    assert rel_l2(to_canonical(host(dA0), "D2Q9"), wlam) < 1e-4
+
+
+def test_autograd_function_matches_adjoint(lbm):
+    """NLBMStep under torch.autograd gives the same gradients as the direct
+    adjoint call (the Function is only plumbing)."""
+    from paper_2403_18466_amd import training
+    ocfg = oracle.Config(nx=20, ny=12, batch=2, tau=0.55, hidden=32, out_scale=0.25)
+    L = lbm.Lattice(lib_config(ocfg))
+    g = dev(to_shifted(random_state(ocfg, 23, scale=0.03), "D2Q9")).requires_grad_(True)
+    th = dev(params(9, 32, seed=24, kind="random")).requires_grad_(True)
+    w = dev(random_state(ocfg, 25, scale=1.0))
+    out = training.NLBMStep.apply(L, g, th)
+    (out * w).sum().backward()
+    lam, dth = L.step_backward(g.detach(), th.detach(), w)
+    assert torch.equal(g.grad, lam) and torch.equal(th.grad, dth)
