@@ -18,7 +18,7 @@
  * Memory.  Every array argument is a DEVICE pointer owned by the caller,
  * contiguous, 4-byte aligned (float) or 8-byte aligned (double).  The library
  * never frees caller memory and keeps no pointer past a call.  The context
- * owns only its configuration.
+ * owns its configuration and a small reduction buffer (see lbm_create).
  *
  * Streams.  Every call that takes a hipStream_t only enqueues work on that
  * stream (pass 0 for the null stream); none synchronises the device.  A call
@@ -114,10 +114,15 @@ typedef struct {
     double out_scale;    /* s_out: the network term is (s_out / tau) * y */
 } lbm_config;
 
-/* Validate `cfg` and create a context holding a copy of it.  Allocates no
- * device memory.  Limits: batch * Q * nx * ny * nz < 2^31 elements and each
- * population array below 4 GiB.  Returns LBM_ERR_INVALID or
- * LBM_ERR_UNSUPPORTED with the reason in lbm_last_error(). */
+/* Validate `cfg` and create a context holding a copy of it, bound to the
+ * current device.  The context allocates one small device buffer
+ * (12 KiB per field) for the float64 partial sums of lbm_moments and
+ * lbm_loss_velocity_mse; calls that use one context must therefore be
+ * ordered (one stream, or synchronised streams).  Limit:
+ * batch * Q * nx * ny * nz < 2^30 elements (each population array below
+ * 4 GiB, the range of the kernels' 32-bit byte offsets).  Returns
+ * LBM_ERR_INVALID or LBM_ERR_UNSUPPORTED with the reason in
+ * lbm_last_error(), LBM_ERR_HIP if the device query or allocation fails. */
 lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out);
 lbm_status lbm_destroy(lbm_ctx* ctx);
 

@@ -33,7 +33,7 @@ __device__ inline void collide_adjoint(const float g[L::Q], const float mu[L::Q]
   constexpr int Q = L::Q;
   float drho, j[3];
   moments<L>(g, drho, j);
-  const float rho = rho0 + drho, inv = 1.f / rho;
+  const float rho = rho0 + drho, inv = __builtin_amdgcn_rcpf(rho);
   const float u[3] = {j[0] * inv, j[1] * inv, j[2] * inv};
   const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
@@ -98,18 +98,6 @@ __device__ inline void collide_adjoint(const float g[L::Q], const float mu[L::Q]
   }
 }
 
-// Scatter l to the pull-shifted positions: lam^n_q(x - c_q) = l_q(x).
-template <class L>
-__device__ inline void scatter(float* __restrict__ out, const Grid& G, int b, int x, int y, int z,
-                               const float v[L::Q]) {
-#pragma unroll
-  for (int q = 0; q < L::Q; ++q) {
-    int xd = wrap_sub(x, L::cx[q], G.nx), yd = wrap_sub(y, L::cy[q], G.ny),
-        zd = wrap_sub(z, L::cz[q], G.nz);
-    out[cell(G, b, q, L::Q, xd, yd, zd)] = v[q];
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Adjoint of the BGK step (no network), one node per thread.
 // ---------------------------------------------------------------------------
@@ -119,17 +107,15 @@ __global__ __launch_bounds__(256) void bgk_backward_kernel(const float* __restri
                                                            float* __restrict__ lam0, Grid G,
                                                            Force Fc, float rho0, float omega,
                                                            int nxc) {
-  const int row = blockIdx.x / nxc, xc = blockIdx.x - row * nxc;
-  const int x = xc * 256 + threadIdx.x;
-  if (x >= G.nx) return;
-  const int y = row % G.ny, t = row / G.ny, z = t % G.nz, b = t / G.nz;
+  const Item t = locate_item(blockIdx.x, nxc, G, threadIdx.x, 256);
+  if (!t.active) return;
+  const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * L::Q) * 4u;
   float g[L::Q], mu[L::Q], nu[L::Q], lam[L::Q], F[3];
-  gather<L>(A, G, b, x, y, z, g);
-#pragma unroll
-  for (int q = 0; q < L::Q; ++q) mu[q] = lam1[cell(G, b, q, L::Q, x, y, z)];
-  body_force(Fc, G, x, y, z, F);
+  gather_item<L>(make_rsrc(A, bytes), G, t, g);
+  load_local<L>(make_rsrc(lam1, bytes), G, t, mu);
+  body_force(Fc, G, t.x, t.y, t.z, F);
   collide_adjoint<L>(g, mu, rho0, omega, F, Fc.kind != 0, nu, lam);
-  scatter<L>(lam0, G, b, x, y, z, lam);
+  scatter_item<L>(make_rsrc(lam0, bytes), G, t, lam);
 }
 
 // ---------------------------------------------------------------------------
@@ -251,21 +237,14 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
 #pragma unroll
   for (int q = 0; q < Q; ++q) db3[q] = 0.f;
 
-  auto locate = [&](int it, int& b, int& x, int& y, int& z) {
-    int row = it / nxc, xc = it - row * nxc;
-    x = xc * 64 + lane;
-    y = row % G.ny;
-    int t = row / G.ny;
-    z = t % G.nz;
-    b = t / G.nz;
-  };
+  const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * Q) * 4u;
+  const rsrc_t rA = make_rsrc(A, bytes), rL1 = make_rsrc(lam1, bytes),
+               rL0 = make_rsrc(lam0, bytes);
   auto load = [&](int it, float g[Q], float mu[Q]) {
-    int b, x, y, z;
-    locate(it, b, x, y, z);
-    if (x < G.nx) {
-      gather<L>(A, G, b, x, y, z, g);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) mu[q] = lam1[cell(G, b, q, Q, x, y, z)];
+    const Item t = locate_item(it, nxc, G, lane);
+    if (t.active) {
+      gather_item<L>(rA, G, t, g);
+      load_local<L>(rL1, G, t, mu);
     } else {
 #pragma unroll
       for (int q = 0; q < Q; ++q) g[q] = mu[q] = 0.f;
@@ -277,10 +256,9 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
   for (int it = it0; it < it1; ++it) {
     float gn[Q], mn[Q];
     if (it + 1 < it1) load(it + 1, gn, mn);
-    int b, x, y, z;
-    locate(it, b, x, y, z);
+    const Item t = locate_item(it, nxc, G, lane);
     float F3[3] = {0.f, 0.f, 0.f};
-    if (Fc.kind != 0) body_force(Fc, G, x, y, z, F3);
+    if (Fc.kind != 0) body_force(Fc, G, t.x, t.y, t.z, F3);
     float nu[Q], lam[Q];
     collide_adjoint<L>(gc, mc, rho0, omega, F3, Fc.kind != 0, nu, lam);
 
@@ -414,7 +392,7 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
     wave_lds_sync();
 #pragma unroll
     for (int q = 0; q < Q; ++q) lam[q] += D[lane * BL::SD + q];
-    if (x < G.nx) scatter<L>(lam0, G, b, x, y, z, lam);
+    if (t.active) scatter_item<L>(rL0, G, t, lam);
     wave_lds_sync();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {

@@ -42,6 +42,143 @@ __device__ inline void gather(const float* __restrict__ A, const Grid& G, int b,
 }
 
 // ---------------------------------------------------------------------------
+// Addressing of a 64-node work item (64 consecutive x of row (b, z, y)) with
+// buffer instructions: the row part of every address is a wave-uniform
+// scalar byte offset, the x part one of three per-lane offsets (x, x - 1,
+// x + 1 with periodic wrap).  Buffer accesses are range-checked by the
+// hardware against the array size.
+// ---------------------------------------------------------------------------
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+__device__ inline rsrc_t make_rsrc(const float* p, unsigned bytes) {
+  // last descriptor dword of gfx9: 32-bit data format, raw (unformatted) access
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+
+struct Item {
+  int b, y, z;    // wave-uniform
+  int x;          // this lane
+  bool active;    // x < nx
+  int vx, vm, vp;  // byte offsets of x, (x - 1) mod nx, (x + 1) mod nx
+};
+
+// Item `it` of width W (64 for the persistent kernels, 256 for one-node-per-
+// thread kernels); nxc = ceil(nx / W) items per row.
+__device__ inline Item locate_item(int it, int nxc, const Grid& G, int lane, int W = 64) {
+  Item t;
+  const int row = it / nxc, xc = it - row * nxc;
+  t.y = row % G.ny;
+  const int r = row / G.ny;
+  t.z = r % G.nz;
+  t.b = r / G.nz;
+  t.x = xc * W + lane;
+  t.active = t.x < G.nx;
+  const int xm = t.x == 0 ? G.nx - 1 : t.x - 1;
+  const int xp = t.x + 1 >= G.nx ? 0 : t.x + 1;
+  t.vx = t.x * 4;
+  t.vm = xm * 4;
+  t.vp = xp * 4;
+  return t;
+}
+
+// Walks consecutive items of a contiguous range without integer division
+// in the loop: `next()` advances x-chunk, then y, z and b.
+struct ItemWalk {
+  int xc, y, z, b;
+  __device__ inline void start(int it, int nxc, const Grid& G) {
+    const int row = it / nxc;
+    xc = it - row * nxc;
+    y = row % G.ny;
+    const int r = row / G.ny;
+    z = r % G.nz;
+    b = r / G.nz;
+  }
+  __device__ inline void next(int nxc, const Grid& G) {
+    if (++xc == nxc) {
+      xc = 0;
+      if (++y == G.ny) {
+        y = 0;
+        if (++z == G.nz) {
+          z = 0;
+          ++b;
+        }
+      }
+    }
+  }
+  // Lane addressing; lanes past the end of the row read node nx - 1 (their
+  // results are never stored).
+  __device__ inline Item item(const Grid& G, int lane, int W = 64) const {
+    Item t;
+    t.b = b;
+    t.y = y;
+    t.z = z;
+    t.x = xc * W + lane;
+    t.active = t.x < G.nx;
+    const int x = t.active ? t.x : G.nx - 1;
+    const int xm = x == 0 ? G.nx - 1 : x - 1;
+    const int xp = x + 1 >= G.nx ? 0 : x + 1;
+    t.vx = x * 4;
+    t.vm = xm * 4;
+    t.vp = xp * 4;
+    return t;
+  }
+};
+
+// Byte offset of the start of row (z, y) of plane q of field b.
+__device__ inline unsigned row_bytes(const Grid& G, int Q, int b, int q, int z, int y) {
+  return (unsigned)(((b * Q + q) * G.nz + z) * G.ny + y) * (unsigned)G.nx * 4u;
+}
+
+// Offsets of A_q(x - c_q): the pull source of population q of this lane's
+// node, which is also the push target of the adjoint.
+template <class L, int q>
+__device__ inline void pull_offsets(const Grid& G, const Item& t, unsigned& so, int& vo) {
+  const int ys = wrap_sub(t.y, L::cy[q], G.ny), zs = wrap_sub(t.z, L::cz[q], G.nz);
+  so = row_bytes(G, L::Q, t.b, q, zs, ys);
+  vo = L::cx[q] > 0 ? t.vm : (L::cx[q] < 0 ? t.vp : t.vx);
+}
+
+template <class L, int q = 0>
+__device__ inline void gather_item(rsrc_t src, const Grid& G, const Item& t, float g[L::Q]) {
+  if constexpr (q < L::Q) {
+    unsigned so;
+    int vo;
+    pull_offsets<L, q>(G, t, so, vo);
+    g[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src, vo, (int)so, 0));
+    gather_item<L, q + 1>(src, G, t, g);
+  }
+}
+
+// Node-local read of all Q planes at this lane's node.
+template <class L>
+__device__ inline void load_local(rsrc_t src, const Grid& G, const Item& t, float v[L::Q]) {
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q)
+    v[q] = __builtin_bit_cast(
+        float, __builtin_amdgcn_raw_buffer_load_b32(src, t.vx, (int)row_bytes(G, L::Q, t.b, q, t.z, t.y), 0));
+}
+
+template <class L>
+__device__ inline void store_local(rsrc_t dst, const Grid& G, const Item& t, const float v[L::Q]) {
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v[q]), dst, t.vx,
+                                          (int)row_bytes(G, L::Q, t.b, q, t.z, t.y), 0);
+}
+
+template <class L, int q = 0>
+__device__ inline void scatter_item(rsrc_t dst, const Grid& G, const Item& t, const float v[L::Q]) {
+  if constexpr (q < L::Q) {
+    unsigned so;
+    int vo;
+    pull_offsets<L, q>(G, t, so, vo);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v[q]), dst, vo, (int)so, 0);
+    scatter_item<L, q + 1>(dst, G, t, v);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Equilibrium initial state: A_q(x - c_q) = f^eq_q(rho(x), u(x)) - w_q rho0.
 // ---------------------------------------------------------------------------
 template <class L>
@@ -180,7 +317,7 @@ __device__ inline void bgk_update(const float g[L::Q], float rho0, float omega, 
   float drho, j[3];
   moments<L>(g, drho, j);
   rho = rho0 + drho;
-  float inv = 1.f / rho;
+  const float inv = __builtin_amdgcn_rcpf(rho);
   u[0] = j[0] * inv;
   u[1] = j[1] * inv;
   u[2] = j[2] * inv;
@@ -199,7 +336,7 @@ __device__ inline void finish_collision(const float g[L::Q], float upd[L::Q], fl
                                         float post[L::Q]) {
   project<L>(upd);
   if (forced) {
-    float inv = 1.f / rho;
+    const float inv = __builtin_amdgcn_rcpf(rho);
     float du[3] = {F[0] * inv, F[1] * inv, F[2] * inv};
     float dd = du[0] * (2.f * u[0] + du[0]) + du[1] * (2.f * u[1] + du[1]) +
                du[2] * (2.f * u[2] + du[2]);
@@ -222,19 +359,17 @@ __global__ __launch_bounds__(256) void bgk_step_kernel(const float* __restrict__
                                                        float* __restrict__ Aout, Grid G,
                                                        Force Fc, float rho0, float omega,
                                                        int nxc) {
-  const int row = blockIdx.x / nxc, xc = blockIdx.x - row * nxc;
-  const int x = xc * 256 + threadIdx.x;
-  if (x >= G.nx) return;
-  const int y = row % G.ny, t = row / G.ny, z = t % G.nz, b = t / G.nz;
+  const Item t = locate_item(blockIdx.x, nxc, G, threadIdx.x, 256);
+  if (!t.active) return;
+  const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * L::Q) * 4u;
   float g[L::Q];
-  gather<L>(Ain, G, b, x, y, z, g);
+  gather_item<L>(make_rsrc(Ain, bytes), G, t, g);
   float upd[L::Q], rho, u[3], F[3];
   bgk_update<L>(g, rho0, omega, upd, rho, u);
-  body_force(Fc, G, x, y, z, F);
+  body_force(Fc, G, t.x, t.y, t.z, F);
   float post[L::Q];
   finish_collision<L>(g, upd, rho, u, F, Fc.kind != 0, post);
-#pragma unroll
-  for (int q = 0; q < L::Q; ++q) Aout[cell(G, b, q, L::Q, x, y, z)] = post[q];
+  store_local<L>(make_rsrc(Aout, bytes), G, t, post);
 }
 
 __device__ inline void wave_lds_sync() {
@@ -292,48 +427,26 @@ __global__ __launch_bounds__(256) void nlbm_step_kernel(const float* __restrict_
   Weights<P, S> W;
   W.load(theta);
 
-  auto locate = [&](int it, int& b, int& x, int& y, int& z) {
-    int row = it / nxc, xc = it - row * nxc;
-    x = xc * 64 + lane;
-    y = row % G.ny;
-    int t = row / G.ny;
-    z = t % G.nz;
-    b = t / G.nz;
-  };
-  auto load = [&](int it, float g[Q]) {
-    int b, x, y, z;
-    locate(it, b, x, y, z);
-    if (x < G.nx) {
-      gather<L>(Ain, G, b, x, y, z, g);
-    } else {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) g[q] = 0.f;
-    }
-  };
+  const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * Q) * 4u;
+  const rsrc_t src = make_rsrc(Ain, bytes), dst = make_rsrc(Aout, bytes);
 
-  float gc[Q];
-  load(it0, gc);
+  // the input columns past the populations never change: a constant 1 for
+  // the bias of layer 1, then zeros
+#pragma unroll
+  for (int k = Q; k < 16 * S::KX; ++k) X[lane * LD::SX + k] = k == Q ? 1.f : 0.f;
+
+  ItemWalk cur, nxt;
+  cur.start(it0, nxc, G);
+  float gn[Q];
+  gather_item<L>(src, G, cur.item(G, lane), gn);
   for (int it = it0; it < it1; ++it) {
-    float gn[Q];
-    if (it + 1 < it1) load(it + 1, gn);
-
-    int b, x, y, z;
-    locate(it, b, x, y, z);
-    float upd[Q], rho, u[3];
-    bgk_update<L>(gc, rho0, omega, upd, rho, u);
-
-    // stage the network input (populations, a constant 1 for the bias
-    // column, zero padding) in node-major rows
+    // this item's populations go to the LDS tile; the next item's loads are
+    // issued before the network runs
 #pragma unroll
-    for (int c = 0; c < 4 * S::KX; ++c) {
-      f4 v;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int k = 4 * c + r;
-        v[r] = k < Q ? gc[k] : (k == Q ? 1.f : 0.f);
-      }
-      *reinterpret_cast<f4*>(X + lane * LD::SX + 4 * c) = v;
-    }
+    for (int q = 0; q < Q; ++q) X[lane * LD::SX + q] = gn[q];
+    nxt = cur;
+    nxt.next(nxc, G);
+    if (it + 1 < it1) gather_item<L>(src, G, nxt.item(G, lane), gn);
     wave_lds_sync();
 #pragma unroll
     for (int jg = 0; jg < 4; ++jg) {
@@ -344,35 +457,33 @@ __global__ __launch_bounds__(256) void nlbm_step_kernel(const float* __restrict_
         xin[c] = to_frag<P>(*reinterpret_cast<const f4*>(X + nrow * LD::SX + 16 * c + 4 * lg));
       F h1[S::HB], h2[S::HB];
 #pragma unroll
-      for (int ob = 0; ob < S::HB; ++ob) {
-        f4 a = mma_row<P, S::KX>(f4{0.f, 0.f, 0.f, 0.f}, W.w1[ob], xin);
-        h1[ob] = to_frag<P>(tanh4<P>(a));
-      }
+      for (int ob = 0; ob < S::HB; ++ob)
+        h1[ob] = to_frag<P>(tanh4<P>(mma_row<P, S::KX>(f4{0.f, 0.f, 0.f, 0.f}, W.w1[ob], xin)));
 #pragma unroll
-      for (int ob = 0; ob < S::HB; ++ob) {
-        f4 a = mma_row<P, S::HB>(W.b2[ob], W.w2[ob], h1);
-        h2[ob] = to_frag<P>(tanh4<P>(a));
-      }
+      for (int ob = 0; ob < S::HB; ++ob)
+        h2[ob] = to_frag<P>(tanh4<P>(mma_row<P, S::HB>(W.b2[ob], W.w2[ob], h1)));
 #pragma unroll
-      for (int ob = 0; ob < S::QB; ++ob) {
-        f4 yv = mma_row<P, S::HB>(W.b3[ob], W.w3[ob], h2);
-        *reinterpret_cast<f4*>(Y + nrow * LD::SY + 16 * ob + 4 * lg) = yv;
-      }
+      for (int ob = 0; ob < S::QB; ++ob)
+        *reinterpret_cast<f4*>(Y + nrow * LD::SY + 16 * ob + 4 * lg) =
+            mma_row<P, S::HB>(W.b3[ob], W.w3[ob], h2);
     }
     wave_lds_sync();
+
+    // node layout: BGK, network term, projection, force, store
+    const Item t = cur.item(G, lane);
+    float g[Q], upd[Q], rho, u[3];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) g[q] = X[lane * LD::SX + q];
+    bgk_update<L>(g, rho0, omega, upd, rho, u);
 #pragma unroll
     for (int q = 0; q < Q; ++q) upd[q] = __builtin_fmaf(knn, Y[lane * LD::SY + q], upd[q]);
-
     float F3[3] = {0.f, 0.f, 0.f};
-    if (Fc.kind != 0) body_force(Fc, G, x, y, z, F3);
+    if (Fc.kind != 0) body_force(Fc, G, t.x, t.y, t.z, F3);
     float post[Q];
-    finish_collision<L>(gc, upd, rho, u, F3, Fc.kind != 0, post);
-    if (x < G.nx) {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) Aout[cell(G, b, q, Q, x, y, z)] = post[q];
-    }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) gc[q] = gn[q];
+    finish_collision<L>(g, upd, rho, u, F3, Fc.kind != 0, post);
+    if (t.active) store_local<L>(dst, G, t, post);
+    wave_lds_sync();
+    cur = nxt;
   }
 }
 

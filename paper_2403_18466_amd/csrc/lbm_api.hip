@@ -83,8 +83,8 @@ lbm_status validate(const lbm_config* c) {
     return fail(LBM_ERR_INVALID, "nx, ny, nz and batch must be >= 1");
   if (c->lattice == LBM_D2Q9 && c->nz != 1) return fail(LBM_ERR_INVALID, "D2Q9 needs nz == 1");
   double elems = (double)c->batch * lattice_q(c->lattice) * c->nx * (double)c->ny * c->nz;
-  if (elems >= 2147483648.0)
-    return fail(LBM_ERR_INVALID, "batch*Q*nx*ny*nz must stay below 2^31 elements");
+  if (elems >= 1073741824.0)
+    return fail(LBM_ERR_INVALID, "batch*Q*nx*ny*nz must stay below 2^30 elements (4 GiB)");
   if (!(c->tau > 0.5) || !std::isfinite(c->tau))
     return fail(LBM_ERR_INVALID, "tau must be finite and > 0.5");
   if (!(c->rho0 > 0.0) || !std::isfinite(c->rho0))

@@ -69,7 +69,7 @@ def test_create_rejects_oversized_grid(lbm):
     c = cfg.c_struct()
     ctx = ctypes.c_void_p()
     assert lib.lbm_create(ctypes.byref(c), ctypes.byref(ctx)) == lbm.LBM_ERR_INVALID
-    assert "2^31" in lib.lbm_last_error().decode()
+    assert "2^30" in lib.lbm_last_error().decode()
 
 
 def test_null_arguments_rejected(lbm):
