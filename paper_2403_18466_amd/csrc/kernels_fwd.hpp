@@ -320,8 +320,8 @@ __device__ inline void bgk_update(const float g[L::Q], float rho0, float omega, 
   const float inv = __builtin_amdgcn_rcpf(rho);
   u[0] = j[0] * inv;
   u[1] = j[1] * inv;
-  u[2] = j[2] * inv;
-  float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  u[2] = L::D == 3 ? j[2] * inv : 0.f;
+  const float uu = dot3<L>(u, u);
   float geq[L::Q];
   Unroll<L>::feq(drho, rho, u, uu, geq);
 #pragma unroll
@@ -338,8 +338,8 @@ __device__ inline void finish_collision(const float g[L::Q], float upd[L::Q], fl
   if (forced) {
     const float inv = __builtin_amdgcn_rcpf(rho);
     float du[3] = {F[0] * inv, F[1] * inv, F[2] * inv};
-    float dd = du[0] * (2.f * u[0] + du[0]) + du[1] * (2.f * u[1] + du[1]) +
-               du[2] * (2.f * u[2] + du[2]);
+    const float u2[3] = {2.f * u[0] + du[0], 2.f * u[1] + du[1], 2.f * u[2] + du[2]};
+    const float dd = dot3<L>(du, u2);
     float fe[L::Q];
     Unroll<L>::fext(rho, u, du, dd, fe);
 #pragma unroll

@@ -73,38 +73,73 @@ __device__ inline void body_force(const Force& f, const Grid& G, int x, int y, i
   }
 }
 
-// Node moments of a deviation vector g (SI: rho = sum f, rho u = sum f c);
-// the w rho0 part sums to rho0 and contributes no momentum.
+// Component a of a velocity vector of population q (compile-time constant).
 template <class L>
-__device__ inline void moments(const float g[L::Q], float& drho, float j[3]) {
-  float s = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-  for (int q = 0; q < L::Q; ++q) {
-    s += g[q];
-    if (L::cx[q] > 0) jx += g[q];
-    if (L::cx[q] < 0) jx -= g[q];
-    if (L::cy[q] > 0) jy += g[q];
-    if (L::cy[q] < 0) jy -= g[q];
-    if (L::cz[q] > 0) jz += g[q];
-    if (L::cz[q] < 0) jz -= g[q];
-  }
-  drho = s;
-  j[0] = jx;
-  j[1] = jy;
-  j[2] = jz;
+__device__ constexpr int comp(int q, int a) {
+  return a == 0 ? L::cx[q] : (a == 1 ? L::cy[q] : L::cz[q]);
 }
 
+// sum_q c_qa v_q with the signs resolved at compile time; the first nonzero
+// term starts the sum (no float additions of zero).
+template <class L, int a, int q = 0>
+__device__ inline float csum_from(const float v[L::Q], float acc, bool started) {
+  if constexpr (q == L::Q) {
+    return started ? acc : 0.f;
+  } else {
+    constexpr int c = comp<L>(q, a);
+    if constexpr (c == 0) {
+      return csum_from<L, a, q + 1>(v, acc, started);
+    } else {
+      const float term = c > 0 ? v[q] : -v[q];
+      return csum_from<L, a, q + 1>(v, started ? acc + term : term, true);
+    }
+  }
+}
+template <class L, int a>
+__device__ inline float csum(const float v[L::Q]) {
+  return csum_from<L, a, 0>(v, 0.f, false);
+}
+template <class L>
+__device__ inline float qsum(const float v[L::Q]) {
+  float s = v[0];
+#pragma unroll
+  for (int q = 1; q < L::Q; ++q) s += v[q];
+  return s;
+}
+
+// Node moments of a deviation vector g (SI: rho = sum f, rho u = sum f c);
+// the w rho0 part sums to rho0 and contributes no momentum.  j[2] = 0 for
+// two-dimensional lattices.
+template <class L>
+__device__ inline void moments(const float g[L::Q], float& drho, float j[3]) {
+  drho = qsum<L>(g);
+  j[0] = csum<L, 0>(g);
+  j[1] = csum<L, 1>(g);
+  j[2] = L::D == 3 ? csum<L, 2>(g) : 0.f;
+}
+
+// c_q . v with compile-time signs (z ignored for two-dimensional lattices).
 template <class L, int q>
 __device__ inline float cdot(const float v[3]) {
   float r = 0.f;
-  if (L::cx[q] > 0) r += v[0];
-  if (L::cx[q] < 0) r -= v[0];
-  if (L::cy[q] > 0) r += v[1];
-  if (L::cy[q] < 0) r -= v[1];
-  if (L::D == 3) {
-    if (L::cz[q] > 0) r += v[2];
-    if (L::cz[q] < 0) r -= v[2];
+  bool started = false;
+#pragma unroll
+  for (int a = 0; a < L::D; ++a) {
+    const int c = comp<L>(q, a);
+    if (c != 0) {
+      const float t = c > 0 ? v[a] : -v[a];
+      r = started ? r + t : t;
+      started = true;
+    }
   }
+  return r;
+}
+
+template <class L>
+__device__ inline float dot3(const float a[3], const float b[3]) {
+  float r = a[0] * b[0];
+  r = __builtin_fmaf(a[1], b[1], r);
+  if constexpr (L::D == 3) r = __builtin_fmaf(a[2], b[2], r);
   return r;
 }
 
@@ -115,9 +150,13 @@ struct Unroll {
   static __device__ inline void feq(float drho, float rho, const float u[3], float uu,
                                     float geq[L::Q]) {
     if constexpr (q < L::Q) {
-      float cu = cdot<L, q>(u);
-      float p = __builtin_fmaf(4.5f * cu, cu, __builtin_fmaf(3.f, cu, -1.5f * uu));
-      geq[q] = L::w[q] * __builtin_fmaf(rho, p, drho);
+      if constexpr (L::cx[q] == 0 && L::cy[q] == 0 && L::cz[q] == 0) {
+        geq[q] = L::w[q] * __builtin_fmaf(rho, -1.5f * uu, drho);
+      } else {
+        float cu = cdot<L, q>(u);
+        float p = __builtin_fmaf(4.5f * cu, cu, __builtin_fmaf(3.f, cu, -1.5f * uu));
+        geq[q] = L::w[q] * __builtin_fmaf(rho, p, drho);
+      }
       Unroll<L, q + 1>::feq(drho, rho, u, uu, geq);
     }
   }
@@ -145,17 +184,18 @@ template <class L>
 __device__ inline void project(float v[L::Q]) {
   float s, m[3];
   moments<L>(v, s, m);
-  float k1 = -s * (1.f / L::Q);
-  float ka[3] = {-m[0] * (1.f / L::csum2), -m[1] * (1.f / L::csum2), -m[2] * (1.f / L::csum2)};
+  const float k1 = -s * (1.f / L::Q);
+  const float ka[3] = {-m[0] * (1.f / L::csum2), -m[1] * (1.f / L::csum2),
+                       -m[2] * (1.f / L::csum2)};
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) {
     float d = k1;
-    if (L::cx[q] > 0) d += ka[0];
-    if (L::cx[q] < 0) d -= ka[0];
-    if (L::cy[q] > 0) d += ka[1];
-    if (L::cy[q] < 0) d -= ka[1];
-    if (L::cz[q] > 0) d += ka[2];
-    if (L::cz[q] < 0) d -= ka[2];
+#pragma unroll
+    for (int a = 0; a < L::D; ++a) {
+      const int c = comp<L>(q, a);
+      if (c > 0) d += ka[a];
+      if (c < 0) d -= ka[a];
+    }
     v[q] += d;
   }
 }
