@@ -40,8 +40,9 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=200)
-    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-train", action="store_true", help="skip the training-step timing")
     p.add_argument("--variants", default="bf16,fp16,fp32,bgk")
     return p.parse_args()
 
@@ -80,6 +81,56 @@ def time_variant(torch, lbm, inputs, prec, hidden, steps, warmup, A0):
     L.close()
     return {"ms_per_step": ms, "mlups": N * N / (ms * 1e-3) / 1e6, "wall_s": wall,
             "mass": float(d[0]), "kinetic_energy": float(d[1]), "nonfinite": int(d[2])}
+
+
+def time_training(torch, lbm, inputs, prec, reps):
+    """One training step of the unrolled-training workload: 8 fields of
+    256 x 256, 32 unrolled steps with a checkpoint every 8 (forward, segment
+    recompute, 32 adjoint steps, loss gradient, Adam), tau' = 0.50125,
+    network 9->64->64->9.  Inputs are synthetic (equilibria of random
+    solenoidal fields); returns the median wall time of `reps` steps and the
+    adjoint-kernel throughput."""
+    from paper_2403_18466_amd import training
+    import numpy as np
+    n, B = 256, 8
+    cfg = lbm.Config(nx=n, ny=n, batch=B, tau=0.50125, hidden=HIDDEN, mlp_prec=prec,
+                     out_scale=2.0 ** -10)
+    L = lbm.Lattice(cfg)
+    u = np.stack([inputs.solenoidal_spectrum_velocity((n, n), 16.0, 0.02, 100 + b)
+                  for b in range(B)]).astype("float32")
+    ud = torch.from_numpy(u).reshape(B, 2, 1, n, n).cuda()
+    A0 = L.init(torch.ones((B, 1, n, n), device="cuda"), ud)
+    ut = torch.from_numpy(0.9 * u).reshape(B, 2, 1, n, n).cuda().contiguous()
+    theta = torch.from_numpy(inputs.glorot_params(9, HIDDEN, seed=1)).cuda()
+    opt = training.Adam(theta, lr=1e-4, weight_decay=1e-6)
+    times = []
+    for r in range(reps + 2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss, dth, _ = training.unrolled_loss_and_grad(L, A0, theta, ut, 32, 8)
+        opt.step(dth)
+        torch.cuda.synchronize()
+        if r >= 2:
+            times.append(time.perf_counter() - t0)
+    # adjoint kernel alone
+    lam = torch.randn_like(A0)
+    out = torch.empty_like(A0)
+    dtheta = torch.zeros(L.n_param, device="cuda")
+    ws = L.workspace()
+    for _ in range(3):
+        lbm.lbm_step_backward(L.ctx, cfg, A0, theta, lam, out, dtheta, ws)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        lbm.lbm_step_backward(L.ctx, cfg, A0, theta, lam, out, dtheta, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_bwd = e0.elapsed_time(e1) / 20
+    L.close()
+    times.sort()
+    return {"train_step_ms": 1e3 * times[len(times) // 2],
+            "adjoint_ms": ms_bwd, "adjoint_mlups": n * n * B / (ms_bwd * 1e-3) / 1e6}
 
 
 def cpu_baseline():
@@ -184,6 +235,16 @@ def main():
                                   "unit": "GB/s",
                                   "frac": BYTES_PER_LUP * N * N / (bgk["ms_per_step"] * 1e-3) /
                                   HBM_PEAK}
+    if not args.no_train:
+        tr = {p: time_training(torch, lbm, inputs, p, 5) for p in ("bf16", "fp32")}
+        for p, v in tr.items():
+            print(f"# training step {p}: {v['train_step_ms']:.2f} ms, adjoint "
+                  f"{v['adjoint_mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        result["training"] = {"workload": "8 x 256^2 D2Q9, 32 unrolled steps, checkpoint every 8, "
+                                          "H=64, forward + recompute + adjoint + Adam",
+                              **{p: v for p, v in tr.items()},
+                              "bf16_over_fp32_step_time": tr["fp32"]["train_step_ms"] /
+                              tr["bf16"]["train_step_ms"]}
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
