@@ -147,19 +147,27 @@ struct BwdLayout {
   static constexpr int SX = 16 * S::KX + 4;   // node-major tile stride (input / input grad)
   static constexpr int SD = 16 * (S::QB > S::KX ? S::QB : S::KX) + 4;
   static constexpr int ST = 20;               // feature-major transpose tile stride
-  static constexpr int per_wave = 64 * SX + 64 * SD + H * ST;
+  // two feature-major transpose tiles: h2 then d2 in the first, h1 then d1
+  // in the second (a wave's LDS accesses complete in issue order, so a tile
+  // can be rewritten once its previous contents have been read)
+  static constexpr int per_wave = 64 * SX + 64 * SD + 2 * H * ST;
 };
 
-// Transpose of a 16x16 chunk in D layout (lane l: rows 4g + r of column i)
+// Transpose of NB 16x16 chunks in D layout (lane l: rows 4g + r of column i)
 // into the "node as contraction" operand layout (lane l: row i, columns
-// 4g + r), through a feature-major scratch tile T of stride ST.
-template <int ST>
-__device__ inline f4 transpose_chunk(float* T, int blk, f4 v, int lg, int li) {
+// 4g + r), through a feature-major scratch tile T of stride ST: all writes,
+// one wave-level LDS ordering point, all reads.
+template <int P, int ST, int NB>
+__device__ inline void transpose_chunks(float* T, const f4 (&v)[NB], typename Frag<P>::T (&out)[NB],
+                                        int lg, int li) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) T[(16 * blk + 4 * lg + r) * ST + li] = v[r];
+  for (int blk = 0; blk < NB; ++blk)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T[(16 * blk + 4 * lg + r) * ST + li] = v[blk][r];
   wave_lds_sync();
-  f4 out = *reinterpret_cast<const f4*>(T + (16 * blk + li) * ST + 4 * lg);
-  return out;
+#pragma unroll
+  for (int blk = 0; blk < NB; ++blk)
+    out[blk] = to_frag<P>(*reinterpret_cast<const f4*>(T + (16 * blk + li) * ST + 4 * lg));
 }
 
 template <class L, int H, int P>
@@ -339,35 +347,24 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
       // weight gradients, contraction over the 16 nodes of the group
       {
         Fr h2T[S::HB];
-#pragma unroll
-        for (int ib = 0; ib < S::HB; ++ib) {
-          h2T[ib] = to_frag<P>(transpose_chunk<BL::ST>(T, ib, t2[ib], lg, li));
-        }
+        transpose_chunks<P, BL::ST, S::HB>(T, t2, h2T, lg, li);
 #pragma unroll
         for (int qc = 0; qc < S::QB; ++qc)
 #pragma unroll
           for (int ib = 0; ib < S::HB; ++ib) dW3[qc][ib] = mma_chunk<P>(dW3[qc][ib], dyT[qc], h2T[ib]);
       }
-      wave_lds_sync();
       {
         Fr h1T[S::HB], d2T[S::HB];
-#pragma unroll
-        for (int ib = 0; ib < S::HB; ++ib) {
-          h1T[ib] = to_frag<P>(transpose_chunk<BL::ST>(T, ib, t1[ib], lg, li));
-        }
-        wave_lds_sync();
-#pragma unroll
-        for (int ob = 0; ob < S::HB; ++ob) d2T[ob] = to_frag<P>(transpose_chunk<BL::ST>(T, ob, d2[ob], lg, li));
+        transpose_chunks<P, BL::ST, S::HB>(T + H * BL::ST, t1, h1T, lg, li);
+        transpose_chunks<P, BL::ST, S::HB>(T, d2, d2T, lg, li);
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob)
 #pragma unroll
           for (int ib = 0; ib < S::HB; ++ib) dW2[ob][ib] = mma_chunk<P>(dW2[ob][ib], d2T[ob], h1T[ib]);
       }
-      wave_lds_sync();
       {
         Fr d1T[S::HB], x0T[S::KX];
-#pragma unroll
-        for (int ob = 0; ob < S::HB; ++ob) d1T[ob] = to_frag<P>(transpose_chunk<BL::ST>(T, ob, d1[ob], lg, li));
+        transpose_chunks<P, BL::ST, S::HB>(T + H * BL::ST, d1, d1T, lg, li);
 #pragma unroll
         for (int c = 0; c < S::KX; ++c) {
           f4 v;
@@ -380,7 +377,6 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
 #pragma unroll
           for (int c = 0; c < S::KX; ++c) dW1[ob][c] = mma_chunk<P>(dW1[ob][c], d1T[ob], x0T[c]);
       }
-      wave_lds_sync();
       // dx = W1^T d1, over the input rows of this group (overwrites the
       // group's own dy rows, which are no longer read)
 #pragma unroll
@@ -401,59 +397,85 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
     }
   }
 
-  // per-wave partials
-  float* pw = part + (size_t)wv * S::n;
+  // Parameter-gradient partials: the four waves of the block are summed in
+  // LDS in wave order (the tiles are free once every wave has left the item
+  // loop), then the block writes one partial vector part[block][param].
+  __syncthreads();
+  float* red = lds;  // S::n floats, fits in the per-wave tiles of the block
+  static_assert(S::n <= 4 * BL::per_wave, "reduction buffer");
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+      auto put = [&](int idx, float v) { red[idx] = w == 0 ? v : red[idx] + v; };
 #pragma unroll
-  for (int ob = 0; ob < S::HB; ++ob) {
+      for (int ob = 0; ob < S::HB; ++ob) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int o = 16 * ob + 4 * lg + r;
+        for (int r = 0; r < 4; ++r) {
+          const int o = 16 * ob + 4 * lg + r;
 #pragma unroll
-      for (int c = 0; c < S::KX; ++c) {
-        const int k = 16 * c + li;
-        if (k < Q) pw[S::oW1 + o * Q + k] = dW1[ob][c][r];
-        else if (k == Q) pw[S::ob1 + o] = dW1[ob][c][r];
+          for (int c = 0; c < S::KX; ++c) {
+            const int k = 16 * c + li;
+            if (k < Q) put(S::oW1 + o * Q + k, dW1[ob][c][r]);
+            else if (k == Q) put(S::ob1 + o, dW1[ob][c][r]);
+          }
+#pragma unroll
+          for (int c = 0; c < S::HB; ++c) put(S::oW2 + o * H + 16 * c + li, dW2[ob][c][r]);
+          float sb = db2[ob][r];
+          sb += __shfl_xor(sb, 8);
+          sb += __shfl_xor(sb, 4);
+          sb += __shfl_xor(sb, 2);
+          sb += __shfl_xor(sb, 1);
+          if (li == 0) put(S::ob2 + o, sb);
+        }
       }
 #pragma unroll
-      for (int c = 0; c < S::HB; ++c) pw[S::oW2 + o * H + 16 * c + li] = dW2[ob][c][r];
-      float s = db2[ob][r];
-      s += __shfl_xor(s, 8);
-      s += __shfl_xor(s, 4);
-      s += __shfl_xor(s, 2);
-      s += __shfl_xor(s, 1);
-      if (li == 0) pw[S::ob2 + o] = s;
+      for (int qc = 0; qc < S::QB; ++qc)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = 16 * qc + 4 * lg + r;
+#pragma unroll
+          for (int c = 0; c < S::HB; ++c)
+            if (q < Q) put(S::oW3 + q * H + 16 * c + li, dW3[qc][c][r]);
+        }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        float sq = db3[q];
+        sq += __shfl_xor(sq, 32);
+        sq += __shfl_xor(sq, 16);
+        sq += __shfl_xor(sq, 8);
+        sq += __shfl_xor(sq, 4);
+        sq += __shfl_xor(sq, 2);
+        sq += __shfl_xor(sq, 1);
+        if (lane == 0) put(S::ob3 + q, sq);
+      }
     }
+    __syncthreads();
   }
-#pragma unroll
-  for (int qc = 0; qc < S::QB; ++qc)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int q = 16 * qc + 4 * lg + r;
-#pragma unroll
-      for (int c = 0; c < S::HB; ++c)
-        if (q < Q) pw[S::oW3 + q * H + 16 * c + li] = dW3[qc][c][r];
-    }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    float s = db3[q];
-    s += __shfl_xor(s, 32);
-    s += __shfl_xor(s, 16);
-    s += __shfl_xor(s, 8);
-    s += __shfl_xor(s, 4);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 1);
-    if (lane == 0) pw[S::ob3 + q] = s;
-  }
+  float* pb = part + (size_t)blockIdx.x * S::n;
+  for (int i = threadIdx.x; i < S::n; i += 256) pb[i] = red[i];
 }
 
-// dtheta[p] += sum over waves w (in order) of part[w][p]; float64 sum.
-__global__ __launch_bounds__(256) void grad_reduce_kernel(const float* __restrict__ part, int nw,
+// dtheta[p] += sum over the nb block partials part[b][p], in float64.
+// Block = 64 parameters x 4 slices; slice s sums b = s, s + 4, ... with two
+// independent accumulators; the four slice sums are combined in slice order.
+// The order is fixed, so the result is bit-reproducible.
+__global__ __launch_bounds__(256) void grad_reduce_kernel(const float* __restrict__ part, int nb,
                                                           int np, float* __restrict__ dtheta) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= np) return;
-  double s = 0.0;
-  for (int w = 0; w < nw; ++w) s += part[(size_t)w * np + p];
-  dtheta[p] += (float)s;
+  const int pl = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + pl;
+  double a0 = 0.0, a1 = 0.0;
+  if (p < np) {
+    int b = sl;
+    for (; b + 4 < nb; b += 8) {
+      a0 += part[(size_t)b * np + p];
+      a1 += part[(size_t)(b + 4) * np + p];
+    }
+    if (b < nb) a0 += part[(size_t)b * np + p];
+  }
+  __shared__ double red[4][64];
+  red[sl][pl] = a0 + a1;
+  __syncthreads();
+  if (sl == 0 && p < np)
+    dtheta[p] += (float)(((red[0][pl] + red[1][pl]) + red[2][pl]) + red[3][pl]);
 }
 
 }  // namespace lbm

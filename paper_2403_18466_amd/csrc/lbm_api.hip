@@ -238,8 +238,8 @@ lbm_status launch_bwd(lbm_ctx* ctx, const float* A, const float* theta, const fl
                      lam1, lam0, part, G, force_of(c), (float)c.rho0, (float)(1.0 / c.tau),
                      (float)(c.out_scale / c.tau), (int)nitems, nxc);
   LBM_LAUNCHED("nlbm_backward_kernel");
-  hipLaunchKernelGGL(grad_reduce_kernel, dim3(blocks_for(nparam)), dim3(256), 0, s, part,
-                     (int)(blocks * 4), nparam, dtheta);
+  hipLaunchKernelGGL(grad_reduce_kernel, dim3(blocks_for(nparam, 64)), dim3(256), 0, s, part,
+                     (int)blocks, nparam, dtheta);
   LBM_LAUNCHED("grad_reduce_kernel");
   return LBM_OK;
 }
@@ -353,7 +353,7 @@ size_t lbm_param_elems(const lbm_ctx* ctx) {
 
 size_t lbm_workspace_bytes(const lbm_ctx* ctx) {
   if (!ctx || ctx->cfg.hidden == 0) return 0;
-  return sizeof(float) * (size_t)bwd_blocks(ctx->ncu) * 4 *
+  return sizeof(float) * (size_t)bwd_blocks(ctx->ncu) *
          param_count(ctx->cfg.lattice, ctx->cfg.hidden);
 }
 
