@@ -43,6 +43,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-train", action="store_true", help="skip the training-step timing")
+    p.add_argument("--no-d3q19", action="store_true", help="skip the D3Q19 256^3 timing")
     p.add_argument("--variants", default="bf16,fp16,fp32,bgk")
     return p.parse_args()
 
@@ -131,6 +132,57 @@ def time_training(torch, lbm, inputs, prec, reps):
     times.sort()
     return {"train_step_ms": 1e3 * times[len(times) // 2],
             "adjoint_ms": ms_bwd, "adjoint_mlups": n * n * B / (ms_bwd * 1e-3) / 1e6}
+
+
+def time_d3q19(torch, lbm, inputs, steps):
+    """The 3-D workload: D3Q19 256^3, tau 0.51, 19->64->64->19 tanh (s_out
+    2^-6) on bf16 matrix cores, initial field with E(k) ~ k^4 exp(-2 (k/4)^2),
+    u_rms 0.04 per component; plain BGK at the same size; the adjoint step."""
+    import numpy as np
+    n = 256
+    u = inputs.solenoidal_spectrum_velocity((n, n, n), 4.0, 0.04, seed=0).astype("float32")
+    ud = torch.from_numpy(u).reshape(1, 3, n, n, n).cuda()
+    del u
+    res = {}
+    for name, hidden in (("bf16", HIDDEN), ("bgk", 0)):
+        cfg = lbm.Config(lattice="D3Q19", nx=n, ny=n, nz=n, tau=TAU, hidden=hidden,
+                         mlp_prec="bf16", out_scale=S_OUT)
+        L = lbm.Lattice(cfg)
+        A = L.init(torch.ones((1, n, n, n), device="cuda"), ud)
+        B = torch.empty_like(A)
+        theta = torch.from_numpy(inputs.glorot_params(19, HIDDEN, seed=1)).cuda() if hidden else None
+        lbm.lbm_step(L.ctx, cfg, A, B, theta, 4)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = lbm.lbm_step(L.ctx, cfg, A, B, theta, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        _, _, diag = L.moments(out, want_fields=False)
+        r = {"ms_per_step": ms, "mlups": n ** 3 / (ms * 1e-3) / 1e6,
+             "hbm_frac": 152 * n ** 3 / (ms * 1e-3) / HBM_PEAK, "nonfinite": int(diag[0, 2].item())}
+        if hidden:
+            lam = torch.randn_like(A)
+            lam0 = torch.empty_like(A)
+            dth = torch.zeros(L.n_param, device="cuda")
+            ws = L.workspace()
+            lbm.lbm_step_backward(L.ctx, cfg, A, theta, lam, lam0, dth, ws)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(8):
+                lbm.lbm_step_backward(L.ctx, cfg, A, theta, lam, lam0, dth, ws)
+            e1.record()
+            torch.cuda.synchronize()
+            r["adjoint_ms"] = e0.elapsed_time(e1) / 8
+            r["adjoint_mlups"] = n ** 3 / (r["adjoint_ms"] * 1e-3) / 1e6
+        del A, B
+        L.close()
+        res[name] = r
+        print(f"# d3q19 256^3 {name}: {r['mlups']:.0f} MLUPS" +
+              (f", adjoint {r['adjoint_mlups']:.0f} MLUPS" if hidden else ""), file=sys.stderr, flush=True)
+    return res
 
 
 def cpu_baseline():
@@ -235,6 +287,8 @@ def main():
                                   "unit": "GB/s",
                                   "frac": BYTES_PER_LUP * N * N / (bgk["ms_per_step"] * 1e-3) /
                                   HBM_PEAK}
+    if not args.no_d3q19:
+        result["d3q19_256"] = time_d3q19(torch, lbm, inputs, max(10, args.steps // 10))
     if not args.no_train:
         tr = {p: time_training(torch, lbm, inputs, p, 5) for p in ("bf16", "fp32")}
         for p, v in tr.items():

@@ -183,3 +183,26 @@ def test_autograd_function_matches_adjoint(lbm):
     (out * w).sum().backward()
     lam, dth = L.step_backward(g.detach(), th.detach(), w)
     assert torch.equal(g.grad, lam) and torch.equal(th.grad, dth)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_unrolled_gradient_d3q19(lbm, prec):
+    """D3Q19, 10^3 with batch 2, 8 unrolled steps with a checkpoint every 4,
+    network 19->64->64->19: the GPU gradient against the oracle's (fp32 within
+    1e-4; bf16 against the emulated-rounding oracle, bound stated)."""
+    from paper_2403_18466_amd import inputs, training
+    n, T = 10, 8
+    ocfg = oracle.Config(lattice="D3Q19", nx=n, ny=n, nz=n, batch=2, tau=0.51, hidden=64,
+                         out_scale=2.0 ** -4, quant="none" if prec == "fp32" else prec)
+    theta = params(19, 64, seed=1)
+    u = np.stack([inputs.solenoidal_spectrum_velocity((n, n, n), 2.0, 0.04, seed=s) for s in (0, 1)])
+    g0 = oracle.init_equilibrium(ocfg, np.ones((2, n, n, n)), u).astype(np.float32).astype(np.float64)
+    ut = (0.9 * u).astype(np.float32).astype(np.float64)
+    wl, wdth, _ = oracle.unrolled_loss_and_grad(ocfg, g0, theta.astype(np.float64), ut, T, ckpt=4)
+    L = lbm.Lattice(lib_config(ocfg, prec))
+    loss, dth, _ = training.unrolled_loss_and_grad(L, dev(to_shifted(g0, "D3Q19")), dev(theta),
+                                                   dev(ut), T, ckpt=4)
+    e = rel_l2(host(dth), wdth)
+    print(f"D3Q19 {prec} unrolled gradient rel L2 {e:.2e}")
+    assert abs(host(loss)[0] - wl) < (1e-5 if prec == "fp32" else 1e-3) * wl
+    assert e < (1e-4 if prec == "fp32" else 3e-2)

@@ -83,3 +83,56 @@ def test_one_step_full_size_sampled(full_input, prec):
         # many-node random states of test_gpu_forward (measured 0.27 here)
         assert e_upd < 0.5 * gap_round and e_state < 1e-4
     L.close()
+
+
+def test_d3q19_256_cubed_one_step_sampled():
+    """D3Q19 256^3 (the 3-D workload: solenoidal field with E(k) ~ k^4
+    exp(-2 (k/4)^2), u_rms 0.04 per component, tau 0.51, 19->64->64->19 tanh,
+    s_out 2^-6), bf16 network, one step, sampled nodes against the oracle's
+    emulated-rounding collision and the plain fp64 one."""
+    from paper_2403_18466_amd import lbm
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    n = 256
+    c19 = np.array(oracle.tables("D3Q19")[0])
+    ocfg = oracle.Config(lattice="D3Q19", nx=n, ny=n, nz=n, tau=0.51, hidden=64,
+                         out_scale=2.0 ** -6)
+    u = inputs.solenoidal_spectrum_velocity((n, n, n), 4.0, 0.04, seed=0)
+    g = oracle.init_equilibrium(ocfg, np.ones((1, n, n, n)), u[None])
+    del u
+    g32 = g.astype(np.float32)
+    del g
+    A = np.empty_like(g32)
+    for q in range(19):
+        A[0, q] = np.roll(g32[0, q], shift=(-c19[q, 2], -c19[q, 1], -c19[q, 0]), axis=(0, 1, 2))
+    theta = inputs.glorot_params(19, 64, seed=1)
+    L = lbm.Lattice(lib_config(ocfg, "bf16"))
+    out = L.step(torch.from_numpy(A).cuda(), torch.from_numpy(theta).cuda(), 1)
+    del A
+    _, _, diag = L.moments(out, want_fields=False)
+    torch.cuda.synchronize()
+    assert int(diag[0, 2].item()) == 0
+    rng = np.random.default_rng(31)
+    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 63)] + \
+        [tuple(p) for p in rng.integers(0, n, size=(21, 3))]
+    zs, ys, xs = (np.array([p[i] for p in pts]) for i in range(3))
+    got = out[0].cpu().numpy()[:, zs, ys, xs].astype(np.float64)
+    one_q = oracle.Config(lattice="D3Q19", nx=1, ny=1, nz=1, tau=0.51, hidden=64,
+                          out_scale=2.0 ** -6, quant="bf16")
+    one_x = oracle.Config(lattice="D3Q19", nx=1, ny=1, nz=1, tau=0.51, hidden=64,
+                          out_scale=2.0 ** -6)
+    th64 = theta.astype(np.float64)
+    want, exact, pre = [], [], []
+    for z, y, x in pts:
+        gg = g32[0, :, z, y, x].astype(np.float64).reshape(1, 19, 1, 1, 1)
+        want.append(oracle.collide(one_q, gg, th64)[0, :, 0, 0, 0])
+        exact.append(oracle.collide(one_x, gg, th64)[0, :, 0, 0, 0])
+        pre.append(gg[0, :, 0, 0, 0])
+    want, exact, pre = np.array(want).T, np.array(exact).T, np.array(pre).T
+    e_upd = np.linalg.norm(got - want) / np.linalg.norm(exact - pre)
+    gap = np.linalg.norm(want - exact) / np.linalg.norm(exact - pre)
+    e_state = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"D3Q19 256^3 bf16: state rel L2 {e_state:.2e}; |gpu - emulated| / |update| {e_upd:.2e}; "
+          f"emulated rounding / |update| {gap:.2e}")
+    assert e_state < 1e-4 and e_upd < 0.5 * gap
+    L.close()
