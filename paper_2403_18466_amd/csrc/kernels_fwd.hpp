@@ -159,6 +159,11 @@ __device__ inline void load_local(rsrc_t src, const Grid& G, const Item& t, floa
         float, __builtin_amdgcn_raw_buffer_load_b32(src, t.vx, (int)row_bytes(G, L::Q, t.b, q, t.z, t.y), 0));
 }
 
+// Cache policy bit "nt" (non-temporal) for stores of a state that the next
+// step reads back from HBM anyway; measured faster in the bandwidth-bound
+// BGK step only.
+constexpr int kStoreNT = 2;
+
 template <class L>
 __device__ inline void store_local(rsrc_t dst, const Grid& G, const Item& t, const float v[L::Q]) {
 #pragma unroll
@@ -354,22 +359,43 @@ __device__ inline void finish_collision(const float g[L::Q], float upd[L::Q], fl
 // BGK stream-collide, one node per thread.  Blocks cover 256 consecutive x
 // of one row (b, z, y); the launch is 1-D over rows x ceil(nx / 256).
 // ---------------------------------------------------------------------------
-template <class L>
+// R rows per thread (more loads in flight per thread); NT: non-temporal
+// stores (the next step reads the output from HBM anyway).
+template <class L, int R, bool NT>
 __global__ __launch_bounds__(256) void bgk_step_kernel(const float* __restrict__ Ain,
                                                        float* __restrict__ Aout, Grid G,
                                                        Force Fc, float rho0, float omega,
                                                        int nxc) {
-  const Item t = locate_item(blockIdx.x, nxc, G, threadIdx.x, 256);
-  if (!t.active) return;
   const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * L::Q) * 4u;
-  float g[L::Q];
-  gather_item<L>(make_rsrc(Ain, bytes), G, t, g);
-  float upd[L::Q], rho, u[3], F[3];
-  bgk_update<L>(g, rho0, omega, upd, rho, u);
-  body_force(Fc, G, t.x, t.y, t.z, F);
-  float post[L::Q];
-  finish_collision<L>(g, upd, rho, u, F, Fc.kind != 0, post);
-  store_local<L>(make_rsrc(Aout, bytes), G, t, post);
+  const rsrc_t src = make_rsrc(Ain, bytes), dst = make_rsrc(Aout, bytes);
+  const int nrow_groups = (G.ny + R - 1) / R;
+  const int xc = blockIdx.x % nxc;
+  const int rg = blockIdx.x / nxc;
+  const int yg = rg % nrow_groups, zb = rg / nrow_groups;
+  float g[R][L::Q];
+  Item t[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int y = yg * R + r;
+    const int yy = y < G.ny ? y : G.ny - 1;
+    t[r] = locate_item((zb * G.ny + yy) * nxc + xc, nxc, G, threadIdx.x, 256);
+    t[r].active = t[r].active && y < G.ny;
+    if (t[r].active) gather_item<L>(src, G, t[r], g[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (!t[r].active) continue;
+    float upd[L::Q], rho, u[3], F[3];
+    bgk_update<L>(g[r], rho0, omega, upd, rho, u);
+    body_force(Fc, G, t[r].x, t[r].y, t[r].z, F);
+    float post[L::Q];
+    finish_collision<L>(g[r], upd, rho, u, F, Fc.kind != 0, post);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, post[q]), dst, t[r].vx,
+                                            (int)row_bytes(G, L::Q, t[r].b, q, t[r].z, t[r].y),
+                                            NT ? kStoreNT : 0);
+  }
 }
 
 __device__ inline void wave_lds_sync() {

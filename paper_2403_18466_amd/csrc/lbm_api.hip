@@ -155,16 +155,23 @@ lbm_status run_moments(lbm_ctx* ctx, const float* A, float* rho, float* u, doubl
   return LBM_OK;
 }
 
-template <class L>
-lbm_status launch_bgk(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t s) {
+template <class L, int R, bool NT>
+lbm_status launch_bgk_v(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t s) {
   Grid G = grid_of(ctx->cfg);
   int nxc = (G.nx + 255) / 256;
-  long long nblk = (long long)nxc * G.ny * G.nz * G.batch;
-  hipLaunchKernelGGL(bgk_step_kernel<L>, dim3((unsigned)nblk), dim3(256), 0, s, Ain, Aout, G,
-                     force_of(ctx->cfg), (float)ctx->cfg.rho0, (float)(1.0 / ctx->cfg.tau),
-                     nxc);
+  long long nblk = (long long)nxc * ((G.ny + R - 1) / R) * G.nz * G.batch;
+  hipLaunchKernelGGL((bgk_step_kernel<L, R, NT>), dim3((unsigned)nblk), dim3(256), 0, s, Ain,
+                     Aout, G, force_of(ctx->cfg), (float)ctx->cfg.rho0,
+                     (float)(1.0 / ctx->cfg.tau), nxc);
   LBM_LAUNCHED("bgk_step_kernel");
   return LBM_OK;
+}
+
+template <class L>
+lbm_status launch_bgk(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t s) {
+  // one node per thread with non-temporal stores measured fastest (more rows
+  // per thread lowered the achieved bandwidth)
+  return launch_bgk_v<L, 1, true>(ctx, Ain, Aout, s);
 }
 
 // Workgroups for a persistent kernel: as many as fit on the chip at once,
