@@ -32,8 +32,23 @@ BYTES_PER_LUP = 72            # 9 float32 read + 9 float32 written per node
 TANH_PER_LUP = 2 * HIDDEN     # two hidden tanh layers
 TRANS_PER_TANH = 2            # exp2 + reciprocal: no tanh instruction exists
 HBM_PEAK = 8.0e12             # B/s, MI355X HBM3E
-# 256 CUs x 4 SIMDs x 8 transcendental lanes per clock x 2.4 GHz
-TRANS_PEAK = 256 * 4 * 8 * 2.4e9
+SIMD_CYCLES = 256 * 4 * 2.4e9  # 256 CUs x 4 SIMDs x 2.4 GHz
+# per SIMD and clock: 16 FP32 VALU lanes (packed FP32 not used), 8 transcendental lanes
+FP32_LANES, TRANS_LANES = 16, 8
+TRANS_PEAK = SIMD_CYCLES * TRANS_LANES
+# Minimal ALU work of the activation per LUP: 128 tanh, each one exp2 + one
+# reciprocal (transcendental) and three FP32 ops (argument scale, 1 + e,
+# 1 - 2r), plus one packed conversion per two activations to the operand
+# format.  In SIMD-cycles per LUP:
+ACT_CYCLES_PER_LUP = (TANH_PER_LUP * (TRANS_PER_TANH / TRANS_LANES + 3 / FP32_LANES)
+                      + TANH_PER_LUP / 2 / FP32_LANES)
+ACT_PEAK_LUPS = SIMD_CYCLES / ACT_CYCLES_PER_LUP
+
+
+# HBM bytes per launch of the bf16 step from rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# each scaled by the factor a plain copy of known size gives (2.000 / 1.000);
+# None until taken for the current kernel (profiles/).
+TRAFFIC_BYTES = 1.2230e9
 
 
 def parse():
@@ -245,15 +260,21 @@ def main():
     t_launch = head["ms_per_step"] * 1e-3
     trans_rate = TANH_PER_LUP * TRANS_PER_TANH * N * N / t_launch
     hbm_rate = BYTES_PER_LUP * N * N / t_launch
+    lups = N * N / t_launch
     roofline = {
         "bound": "alu",
-        "achieved": trans_rate / 1e12,
-        "peak": TRANS_PEAK / 1e12,
-        "unit": "Ttrans/s",
-        "frac": trans_rate / TRANS_PEAK,
-        "traffic": None,
+        "achieved": lups / 1e9,
+        "peak": ACT_PEAK_LUPS / 1e9,
+        "unit": "GLUP/s (activation ALU ceiling: 128 tanh x (2 transcendental + 3 FP32) + "
+                "64 conversions per LUP at 8 / 16 lanes per clock per SIMD)",
+        "frac": lups / ACT_PEAK_LUPS,
+        "traffic": TRAFFIC_BYTES,
+        "trans_achieved_Tps": trans_rate / 1e12,
+        "trans_peak_Tps": TRANS_PEAK / 1e12,
+        "trans_frac": trans_rate / TRANS_PEAK,
         "hbm_achieved_GBps": hbm_rate / 1e9,
         "hbm_frac": hbm_rate / HBM_PEAK,
+        "mfma_frac": 10496 * lups / 2.5e15,
         "kernel": "nlbm_step_kernel<D2Q9, 64, bf16>",
     }
     bgk = variants.get("bgk")
