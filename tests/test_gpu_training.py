@@ -18,8 +18,8 @@ def data():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2403_18466_amd import coarse_training as ct
-    spec = dict(n_fine=256, cg=4, k0=16.0, urms=0.04, spinup=256, unroll=8)
-    tr = ct.build_dataset(ct.DatasetSpec(n_snap=4, seeds=(100, 101, 102, 103), **spec))
+    spec = dict(n_fine=512, cg=4, k0=32.0, urms=0.04, spinup=1024, unroll=8)
+    tr = ct.build_dataset(ct.DatasetSpec(n_snap=6, seeds=(100, 101, 102, 103), **spec))
     ho = ct.build_dataset(ct.DatasetSpec(n_snap=5, seeds=(200, 201), **spec))
     return ct, tr, ho
 
@@ -46,20 +46,26 @@ def test_gradient_is_descent_direction(data):
     L.close()
 
 
-def test_training_runs_and_reports_gain(data):
+def test_training_gains_over_bgk(data):
+    """Full-batch unrolled training (horizon 16 coarse steps, the output layer
+    starting at zero so the initial model is exactly BGK) lowers the held-out
+    velocity error below plain BGK at the coarse tau'.  The factor is
+    measured; the assertion is only that the trained model is better than
+    BGK at the trained horizon and not worse beyond it by more than 5%."""
     from paper_2403_18466_amd import inputs
     ct, tr, ho = data
-    th0 = torch.from_numpy(inputs.glorot_params(9, 64, seed=1)).cuda()
-    spec = ct.TrainSpec(prec="bf16", epochs=60, lr=1e-3, out_scale=2.0 ** -10, log_every=20)
+    spec = ct.TrainSpec(prec="bf16", epochs=80, horizon=2, ckpt=8, log_every=20)
+    th0 = ct.initial_params(spec)
     theta, hist = ct.train(tr, spec, theta=th0.clone(), log=None)
     assert all(np.isfinite(l) for _, l in hist)
-    assert (theta - th0).abs().max().item() > 1e-3
+    assert hist[-1][1] < hist[0][1]
     ks = [1, 2, 4]
     bgk = ct.rollout_mse(ho, None, 64, "bf16", 1.0, ks)
-    untrained = ct.rollout_mse(ho, th0, 64, "bf16", 2.0 ** -10, ks)
-    trained = ct.rollout_mse(ho, theta, 64, "bf16", 2.0 ** -10, ks)
+    trained = ct.rollout_mse(ho, theta, 64, "bf16", spec.out_scale, ks)
     for k in ks:
         assert bgk[k][1] == 0 and trained[k][1] == 0
         print(f"held-out velocity MSE after {k * ho.spec.unroll} coarse steps: BGK {bgk[k][0]:.4e}, "
-              f"untrained {untrained[k][0]:.4e}, trained {trained[k][0]:.4e}, "
-              f"trained/BGK {trained[k][0] / bgk[k][0]:.4f}")
+              f"trained {trained[k][0]:.4e}, trained/BGK {trained[k][0] / bgk[k][0]:.4f}")
+    print("training loss", hist)
+    assert trained[2][0] < bgk[2][0]
+    assert trained[4][0] < 1.05 * bgk[4][0]
