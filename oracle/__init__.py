@@ -28,6 +28,7 @@ _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 LATTICES = {"D2Q9": 0, "D3Q19": 1}
 QUANT = {"none": 0, "bf16": 1, "fp16": 2}
+NETS = {"tanh": 0, "paper": 1}
 
 
 def build(force: bool = False) -> str:
@@ -49,6 +50,7 @@ class _Cfg(ctypes.Structure):
         ("force_kind", ctypes.c_int32), ("force_amp", ctypes.c_double),
         ("force_k", ctypes.c_int32), ("hidden", ctypes.c_int32),
         ("quant", ctypes.c_int32), ("out_scale", ctypes.c_double),
+        ("net", ctypes.c_int32),
     ]
 
 
@@ -64,7 +66,7 @@ def _load():
         _lib.orc_tables.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                     ctypes.POINTER(ctypes.c_int),
                                     ctypes.POINTER(ctypes.c_int), dp]
-        _lib.orc_param_elems.argtypes = [ctypes.c_int, ctypes.c_int]
+        _lib.orc_param_elems.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
         _lib.orc_param_elems.restype = ctypes.c_int64
         for name, args in [
             ("orc_step", [cp, dp, dp, dp]),
@@ -107,11 +109,12 @@ class Config:
     hidden: int = 0
     quant: str = "none"
     out_scale: float = 1.0
+    net: str = "tanh"      # "tanh": Q-H-H-Q tanh; "paper": Q-300-300-100-Q LeakyReLU
 
     def _c(self) -> _Cfg:
         return _Cfg(LATTICES[self.lattice], self.nx, self.ny, self.nz, self.batch,
                     self.tau, self.rho0, self.force_kind, self.force_amp, self.force_k,
-                    self.hidden, QUANT[self.quant], self.out_scale)
+                    self.hidden, QUANT[self.quant], self.out_scale, NETS[self.net])
 
     @property
     def Q(self) -> int:
@@ -127,7 +130,7 @@ class Config:
 
     @property
     def n_params(self) -> int:
-        return int(_load().orc_param_elems(LATTICES[self.lattice], self.hidden))
+        return int(_load().orc_param_elems(LATTICES[self.lattice], self.hidden, NETS[self.net]))
 
 
 def tables(lattice: str):
@@ -147,6 +150,8 @@ def _theta(cfg: Config, theta):
     if cfg.hidden == 0:
         return None
     t = np.ascontiguousarray(theta, dtype=np.float64)
+    if cfg.n_params == 0:
+        raise ValueError(f"invalid network: hidden={cfg.hidden}, net={cfg.net!r}")
     assert t.size == cfg.n_params, (t.size, cfg.n_params)
     return t
 

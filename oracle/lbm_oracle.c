@@ -20,7 +20,8 @@
  *   moments      rho = sum f, rho u = sum f c                   (SI, moments)
  *   equilibrium  2nd-order polynomial f^eq(rho, u)              (eq. feq)
  *   BGK          Omega = -(1/tau)(f - f^eq), dt = 1             (eq. bgk-sm)
- *   network      y = W3 tanh(W2 tanh(W1 g + b1) + b2) + b3      (SI, MLP)
+ *   network      y = MLP(g): tanh net Q-H-H-Q, or the SI's net
+ *                Q-300-300-100-Q with LeakyReLU                 (SI, MLP)
  *   update       Omega + (s_out/tau) y                          (eq. nn-model-full)
  *   projection   remove the components along 1 and c_alpha      (SI, kappa layer)
  *   forcing      f^eq(rho, u + F/rho) - f^eq(rho, u)            (eq. fext, EDM)
@@ -63,6 +64,8 @@ static const double D2Q9_W[9] = {
 
 #define QMAX 19
 #define HMAX 512
+#define NLMAX 4       /* linear layers of the largest network */
+#define LEAKY_SLOPE 0.01
 
 typedef struct {
     int32_t lattice; /* 0 = D2Q9, 1 = D3Q19 */
@@ -75,6 +78,8 @@ typedef struct {
     int32_t hidden;     /* 0 = plain BGK */
     int32_t quant;      /* 0 exact; 1 bf16; 2 fp16 rounding at the MLP operands */
     double out_scale;   /* s_out: the network update is (s_out / tau) y */
+    int32_t net;        /* 0: Q-H-H-Q, tanh; 1: the SI's Q-300-300-100-Q, LeakyReLU
+                           (hidden must be 300) */
 } orc_config;
 
 typedef struct {
@@ -107,13 +112,44 @@ int orc_tables(int lattice, int *Q, int *D, int *c, double *w) {
     return 0;
 }
 
-/* Number of packed parameters: [W1 (H x Q), b1 (H), W2 (H x H), b2 (H),
- * W3 (Q x H), b3 (Q)], each matrix row-major [out][in]. */
-int64_t orc_param_elems(int lattice, int hidden) {
+/* Layer widths of the network.  net 0: Q -> H -> H -> Q with tanh after the
+ * two hidden layers (the workload's small network).  net 1: the network of
+ * the SI ("Neural Network Architecture and Optimization"): Q -> 300 -> 300 ->
+ * 100 -> Q with LeakyReLU after the three hidden layers; the SI does not give
+ * the negative slope, 0.01 is taken.  The output layer is linear in both. */
+typedef struct {
+    int nl;                 /* number of linear layers (0: no network) */
+    int width[NLMAX + 1];   /* width[0] = width[nl] = Q */
+    int leaky;              /* hidden activation: 0 tanh, 1 LeakyReLU */
+} net_shape;
+
+static int get_net(int Q, int hidden, int net, net_shape *n) {
+    memset(n, 0, sizeof(*n));
+    if (hidden == 0) return 0;
+    if (net == 0) {
+        if (hidden < 0 || hidden > HMAX) return -1;
+        n->nl = 3;
+        n->width[0] = Q; n->width[1] = hidden; n->width[2] = hidden; n->width[3] = Q;
+        return 0;
+    }
+    if (net == 1) {
+        if (hidden != 300) return -1;
+        n->nl = 4; n->leaky = 1;
+        n->width[0] = Q; n->width[1] = 300; n->width[2] = 300; n->width[3] = 100; n->width[4] = Q;
+        return 0;
+    }
+    return -1;
+}
+
+/* Number of packed parameters: for each layer l in order, W_l (row-major
+ * [out][in]) followed by b_l.  For net 0 this is [W1 b1 W2 b2 W3 b3]. */
+int64_t orc_param_elems(int lattice, int hidden, int net) {
     lattice_t L;
-    if (get_lattice(lattice, &L) || hidden <= 0) return 0;
-    int64_t Q = L.Q, H = hidden;
-    return H * Q + H + H * H + H + Q * H + Q;
+    net_shape n;
+    if (get_lattice(lattice, &L) || get_net(L.Q, hidden, net, &n)) return 0;
+    int64_t tot = 0;
+    for (int l = 0; l < n.nl; ++l) tot += (int64_t)n.width[l + 1] * (n.width[l] + 1);
+    return tot;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -212,54 +248,54 @@ static void project(const lattice_t *L, double v[]) {
         v[q] += k1 + k[0] * L->c[q][0] + k[1] * L->c[q][1] + k[2] * L->c[q][2];
 }
 
-/* Parameter views into the packed buffer. */
-typedef struct {
-    const double *W1, *b1, *W2, *b2, *W3, *b3;
-} mlp_view;
-
-static mlp_view mlp_unpack(const double *theta, int Q, int H) {
-    mlp_view m;
-    m.W1 = theta;
-    m.b1 = m.W1 + (int64_t)H * Q;
-    m.W2 = m.b1 + H;
-    m.b2 = m.W2 + (int64_t)H * H;
-    m.W3 = m.b2 + H;
-    m.b3 = m.W3 + (int64_t)Q * H;
-    return m;
-}
-
 /* Saved forward quantities of one node, needed by the adjoint. */
 typedef struct {
     double g[QMAX];
     double drho, j[3], F[3];
     double x0[QMAX];
-    double h1[HMAX], h2[HMAX];     /* activations after tanh (and rounding) */
-    double t1[HMAX], t2[HMAX];     /* tanh values before rounding */
+    double pre[NLMAX][HMAX];  /* hidden pre-activations */
+    double t[NLMAX][HMAX];    /* activation values before rounding */
+    double h[NLMAX][HMAX];    /* activations as the next layer reads them */
     double y[QMAX];
 } node_fwd;
 
-/* The MLP of the SI (three linear layers, two hidden activations), with the
- * activation tanh.  Weights are the (optionally rounded) packed parameters. */
-static void mlp_forward(const orc_config *cfg, const lattice_t *L, const mlp_view *p,
+static double activation(int leaky, double a) {
+    if (leaky) return a > 0.0 ? a : LEAKY_SLOPE * a;
+    return tanh(a);
+}
+
+/* Derivative of the activation, from the pre-activation a and the value t. */
+static double activation_slope(int leaky, double a, double t) {
+    if (leaky) return a > 0.0 ? 1.0 : LEAKY_SLOPE;
+    return 1.0 - t * t; /* tanh' = 1 - tanh^2 */
+}
+
+/* The MLP of the SI: linear layers with the hidden activation after every
+ * layer but the last.  In the emulated reduced-precision mode the network
+ * input, the weights, the layer-1 bias and every hidden activation are
+ * rounded; the other biases and all sums stay exact. */
+static void mlp_forward(const orc_config *cfg, const net_shape *n, const double *theta,
                         node_fwd *s) {
-    int Q = L->Q, H = cfg->hidden, qt = cfg->quant;
-    for (int i = 0; i < Q; ++i) s->x0[i] = quantise(qt, s->g[i]);
-    for (int o = 0; o < H; ++o) {
-        double a = p->b1[o];
-        for (int i = 0; i < Q; ++i) a += quantise(qt, p->W1[(int64_t)o * Q + i]) * s->x0[i];
-        s->t1[o] = tanh(a);
-        s->h1[o] = quantise(qt, s->t1[o]);
-    }
-    for (int o = 0; o < H; ++o) {
-        double a = p->b2[o];
-        for (int i = 0; i < H; ++i) a += quantise(qt, p->W2[(int64_t)o * H + i]) * s->h1[i];
-        s->t2[o] = tanh(a);
-        s->h2[o] = quantise(qt, s->t2[o]);
-    }
-    for (int o = 0; o < Q; ++o) {
-        double a = p->b3[o];
-        for (int i = 0; i < H; ++i) a += quantise(qt, p->W3[(int64_t)o * H + i]) * s->h2[i];
-        s->y[o] = a;
+    int qt = cfg->quant;
+    for (int i = 0; i < n->width[0]; ++i) s->x0[i] = quantise(qt, s->g[i]);
+    const double *in = s->x0;
+    const double *W = theta;
+    for (int l = 0; l < n->nl; ++l) {
+        int nin = n->width[l], nout = n->width[l + 1];
+        const double *b = W + (int64_t)nout * nin;
+        for (int o = 0; o < nout; ++o) {
+            double a = l == 0 ? quantise(qt, b[o]) : b[o];
+            for (int i = 0; i < nin; ++i) a += quantise(qt, W[(int64_t)o * nin + i]) * in[i];
+            if (l + 1 < n->nl) {
+                s->pre[l][o] = a;
+                s->t[l][o] = activation(n->leaky, a);
+                s->h[l][o] = quantise(qt, s->t[l][o]);
+            } else {
+                s->y[o] = a;
+            }
+        }
+        in = s->h[l];
+        W = b + nout;
     }
 }
 
@@ -272,8 +308,9 @@ static void collide_node(const orc_config *cfg, const lattice_t *L, const double
     equilibrium_dev(L, cfg->rho0, s->drho, s->j, geq);
     for (int q = 0; q < Q; ++q) upd[q] = -(s->g[q] - geq[q]) / cfg->tau;
     if (cfg->hidden > 0) {
-        mlp_view p = mlp_unpack(theta, Q, cfg->hidden);
-        mlp_forward(cfg, L, &p, s);
+        net_shape n;
+        get_net(Q, cfg->hidden, cfg->net, &n);
+        mlp_forward(cfg, &n, theta, s);
         double k = cfg->out_scale / cfg->tau;
         for (int q = 0; q < Q; ++q) upd[q] += k * s->y[q];
     }
@@ -296,7 +333,8 @@ static int check_cfg(const orc_config *cfg, lattice_t *L) {
     if (get_lattice(cfg->lattice, L)) return -1;
     if (cfg->nx <= 0 || cfg->ny <= 0 || cfg->nz <= 0 || cfg->batch <= 0) return -1;
     if (L->D == 2 && cfg->nz != 1) return -1;
-    if (cfg->hidden < 0 || cfg->hidden > HMAX) return -1;
+    net_shape n;
+    if (get_net(L->Q, cfg->hidden, cfg->net, &n)) return -1;
     return 0;
 }
 
@@ -498,42 +536,37 @@ static void collide_node_adjoint(const orc_config *cfg, const lattice_t *L, cons
         lam[q] += Grho + Gj[0] * L->c[q][0] + Gj[1] * L->c[q][1] + Gj[2] * L->c[q][2];
 
     if (cfg->hidden > 0) {
-        int H = cfg->hidden, qt = cfg->quant;
-        mlp_view p = mlp_unpack(theta, Q, H);
-        double *dW1 = dtheta, *db1 = dW1 + (int64_t)H * Q, *dW2 = db1 + H;
-        double *db2 = dW2 + (int64_t)H * H, *dW3 = db2 + H, *db3 = dW3 + (int64_t)Q * H;
-        double dy[QMAX], da2[HMAX], da1[HMAX];
+        net_shape n;
+        get_net(Q, cfg->hidden, cfg->net, &n);
+        int qt = cfg->quant;
+        /* parameter offsets of every layer */
+        int64_t off[NLMAX + 1];
+        off[0] = 0;
+        for (int l = 0; l < n.nl; ++l)
+            off[l + 1] = off[l] + (int64_t)n.width[l + 1] * (n.width[l] + 1);
+        double dz[HMAX], din[HMAX];
         double k = cfg->out_scale / tau;
-        for (int q = 0; q < Q; ++q) dy[q] = k * nu[q];
-        /* y = W3 h2 + b3 */
-        for (int o = 0; o < Q; ++o) {
-            db3[o] += dy[o];
-            for (int i = 0; i < H; ++i) dW3[(int64_t)o * H + i] += dy[o] * s->h2[i];
-        }
-        for (int i = 0; i < H; ++i) {
-            double d = 0.0;
-            for (int o = 0; o < Q; ++o) d += quantise(qt, p.W3[(int64_t)o * H + i]) * dy[o];
-            da2[i] = d * (1.0 - s->t2[i] * s->t2[i]); /* tanh' = 1 - tanh^2 */
-        }
-        /* h2 = tanh(W2 h1 + b2) */
-        for (int o = 0; o < H; ++o) {
-            db2[o] += da2[o];
-            for (int i = 0; i < H; ++i) dW2[(int64_t)o * H + i] += da2[o] * s->h1[i];
-        }
-        for (int i = 0; i < H; ++i) {
-            double d = 0.0;
-            for (int o = 0; o < H; ++o) d += quantise(qt, p.W2[(int64_t)o * H + i]) * da2[o];
-            da1[i] = d * (1.0 - s->t1[i] * s->t1[i]);
-        }
-        /* h1 = tanh(W1 x0 + b1), x0 = g */
-        for (int o = 0; o < H; ++o) {
-            db1[o] += da1[o];
-            for (int i = 0; i < Q; ++i) dW1[(int64_t)o * Q + i] += da1[o] * s->x0[i];
-        }
-        for (int i = 0; i < Q; ++i) {
-            double d = 0.0;
-            for (int o = 0; o < H; ++o) d += quantise(qt, p.W1[(int64_t)o * Q + i]) * da1[o];
-            lam[i] += d;
+        for (int q = 0; q < Q; ++q) dz[q] = k * nu[q]; /* output layer is linear */
+        for (int l = n.nl - 1; l >= 0; --l) {
+            int nin = n.width[l], nout = n.width[l + 1];
+            const double *W = theta + off[l];
+            double *dW = dtheta + off[l], *db = dW + (int64_t)nout * nin;
+            const double *in = l == 0 ? s->x0 : s->h[l - 1];
+            for (int o = 0; o < nout; ++o) {
+                db[o] += dz[o];
+                for (int i = 0; i < nin; ++i) dW[(int64_t)o * nin + i] += dz[o] * in[i];
+            }
+            for (int i = 0; i < nin; ++i) {
+                double d = 0.0;
+                for (int o = 0; o < nout; ++o) d += quantise(qt, W[(int64_t)o * nin + i]) * dz[o];
+                din[i] = d;
+            }
+            if (l > 0) {
+                for (int i = 0; i < nin; ++i)
+                    dz[i] = din[i] * activation_slope(n.leaky, s->pre[l - 1][i], s->t[l - 1][i]);
+            } else {
+                for (int i = 0; i < nin; ++i) lam[i] += din[i];
+            }
         }
     }
 }
@@ -547,7 +580,7 @@ int orc_step_adjoint(const orc_config *cfg, const double *theta, const double *g
     lattice_t L;
     if (check_cfg(cfg, &L)) return -1;
     int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q, N = nx * ny * nz;
-    int64_t P = orc_param_elems(cfg->lattice, cfg->hidden);
+    int64_t P = orc_param_elems(cfg->lattice, cfg->hidden, cfg->net);
     double *scratch_dtheta = NULL;
     if (cfg->hidden > 0 && !dtheta) {
         scratch_dtheta = (double *)calloc((size_t)P, sizeof(double));

@@ -149,3 +149,47 @@ def random_params(Q: int, H: int, seed: int, scale: float = 0.3) -> np.ndarray:
     for tests that must exercise nonzero biases."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-scale, scale, size=param_count(Q, H)).astype(np.float32)
+
+
+# The network of the SI: hidden widths of the three LeakyReLU layers.
+PAPER_WIDTHS = (300, 300, 100)
+
+
+def net_widths(Q: int, H: int, net: str = "tanh") -> tuple:
+    """Layer widths (input, hidden..., output) of a network kind."""
+    if net == "tanh":
+        return (Q, H, H, Q)
+    if net == "paper":
+        return (Q,) + PAPER_WIDTHS + (Q,)
+    raise ValueError(f"unknown network kind {net!r}")
+
+
+def net_param_count(widths) -> int:
+    """Packed length: for each layer, W (out x in, row-major) then b."""
+    return sum(widths[l + 1] * (widths[l] + 1) for l in range(len(widths) - 1))
+
+
+def glorot_params_net(widths, seed: int) -> np.ndarray:
+    """Glorot-uniform weights and zero biases for any layer list, drawn layer
+    by layer from default_rng(seed), rounded to float32.  For (Q, H, H, Q)
+    this equals glorot_params(Q, H, seed)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l in range(len(widths) - 1):
+        fi, fo = widths[l], widths[l + 1]
+        a = math.sqrt(6.0 / (fi + fo))
+        W = rng.uniform(-a, a, size=(fo, fi))
+        parts += [W.ravel(), np.zeros(fo)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def random_params_net(widths, seed: int, scale: float = 0.3, bias: float | None = None) -> np.ndarray:
+    """Every weight ~ U(-scale, scale), every bias ~ U(-bias, bias) (bias =
+    scale by default), packed per layer, float32."""
+    rng = np.random.default_rng(seed)
+    b = scale if bias is None else bias
+    parts = []
+    for l in range(len(widths) - 1):
+        fi, fo = widths[l], widths[l + 1]
+        parts += [rng.uniform(-scale, scale, size=fo * fi), rng.uniform(-b, b, size=fo)]
+    return np.concatenate(parts).astype(np.float32)

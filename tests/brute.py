@@ -76,9 +76,35 @@ def mlp(theta, x, H):
     return W3 @ h2 + b3[:, None]
 
 
-def step(g, nx, ny, tau, rho0=1.0, theta=None, H=0, out_scale=1.0, force=None):
+def leaky(z, slope=0.01):
+    """LeakyReLU on real or complex arrays; the branch is chosen by the real
+    part, so complex-step derivatives are exact away from the kink."""
+    return np.where(np.real(z) > 0, z, slope * z)
+
+
+def mlp_paper(theta, x, widths=(300, 300, 100)):
+    """The SI's network for x of shape (Q, N): three LeakyReLU layers of the
+    given widths, then a linear layer back to Q; parameters packed per layer
+    as W (out x in, row-major) then b."""
+    Q = x.shape[0]
+    dims = (Q,) + tuple(widths) + (Q,)
+    o = 0
+    h = x
+    for l in range(len(dims) - 1):
+        nin, nout = dims[l], dims[l + 1]
+        W = theta[o:o + nout * nin].reshape(nout, nin); o += nout * nin
+        b = theta[o:o + nout]; o += nout
+        h = W @ h + b[:, None]
+        if l + 2 < len(dims):
+            h = leaky(h)
+    assert o == theta.size
+    return h
+
+
+def step(g, nx, ny, tau, rho0=1.0, theta=None, H=0, out_scale=1.0, force=None, net="tanh"):
     """One step on a flattened canonical state g of length 9 nx ny (deviations).
-    force: (Fx, Fy) arrays of shape (N,) or None."""
+    force: (Fx, Fy) arrays of shape (N,) or None.  net "paper" uses the SI's
+    LeakyReLU network (H is then ignored, theta selects it)."""
     N = nx * ny
     M = raw_moment_matrix()
     Minv = np.linalg.inv(M)
@@ -88,7 +114,9 @@ def step(g, nx, ny, tau, rho0=1.0, theta=None, H=0, out_scale=1.0, force=None):
     rho, jx, jy = m[0], m[1], m[2]
     meq = eq_moments(rho, jx, jy)
     upd = Minv @ ((meq - m) / tau)
-    if theta is not None and H > 0:
+    if theta is not None and net == "paper":
+        upd = upd + (out_scale / tau) * mlp_paper(theta, gq)
+    elif theta is not None and H > 0:
         upd = upd + (out_scale / tau) * mlp(theta, gq, H)
     upd = projector() @ upd
     post = gq + upd

@@ -582,7 +582,8 @@ def test_velocity_mse_loss_definition():
 # --------------------------------------------------------------------------
 # P14: emulated reduced-precision network.  The same collision written as
 # matrix products with torch's own float32 -> bfloat16 / float16 conversions
-# at the stated rounding points (input, both hidden activations, weights).
+# at the stated rounding points (input, both hidden activations, weights and
+# the layer-1 bias, which the network reads as one more input column).
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("quant", ["bf16", "fp16"])
@@ -596,10 +597,20 @@ def test_emulated_quantisation_points(quant):
     g = _rand_state(cfg_q, 27, scale=0.05)
 
     def rnd(a):
-        # float64 -> float32 is exact for every value rounded here except the
-        # activations; those are first rounded to float32 by torch, which can
-        # only differ from direct rounding at double-rounding ties
-        return torch.from_numpy(np.asarray(a, np.float64)).to(dt).to(torch.float64).numpy()
+        # weights and biases are float32 numbers, which torch rounds
+        # to the 16-bit format exactly once
+        a = np.asarray(a, np.float64)
+        assert np.array_equal(a.astype(np.float32).astype(np.float64), a)
+        return torch.from_numpy(a).to(dt).to(torch.float64).numpy()
+
+    def rnd_act(a):
+        # the state and the activations are float64; torch would round them to float32 first
+        # (a double rounding that can differ at ties), so they are rounded
+        # directly: numpy's float64 -> float16 conversion, or the bfloat16
+        # rounding pinned against torch above
+        if quant == "fp16":
+            return np.asarray(a, np.float64).astype(np.float16).astype(np.float64)
+        return np.vectorize(oracle.round_bf16)(a)
 
     o = 0
     W1 = theta[o:o + H * 9].reshape(H, 9); o += H * 9
@@ -608,9 +619,9 @@ def test_emulated_quantisation_points(quant):
     b2 = theta[o:o + H]; o += H
     W3 = theta[o:o + 9 * H].reshape(9, H); o += 9 * H
     b3 = theta[o:o + 9]
-    x0 = rnd(g.reshape(9, -1))
-    h1 = rnd(np.tanh(rnd(W1) @ x0 + b1[:, None]))
-    h2 = rnd(np.tanh(rnd(W2) @ h1 + b2[:, None]))
+    x0 = rnd_act(g.reshape(9, -1))
+    h1 = rnd_act(np.tanh(rnd(W1) @ x0 + rnd(b1)[:, None]))
+    h2 = rnd_act(np.tanh(rnd(W2) @ h1 + b2[:, None]))
     y = rnd(W3) @ h2 + b3[:, None]
     P = brute.projector()
     want = (oracle.collide(cfg_0, g).reshape(9, -1) + P @ ((s / tau) * y)).reshape(g.shape)
