@@ -51,12 +51,16 @@
  * canonical node-local form.  Storing deviations rather than f keeps the
  * float32 mantissa for the fluctuation instead of the constant w rho0.
  *
- * Network.  Q -> H -> H -> Q with tanh after the two hidden layers and a
- * linear output layer; its output y enters the collision as (s_out/tau) y
- * and the whole collision update is projected off span{1, c_x, c_y[, c_z]}.
- * Parameters are one packed float32 vector (length lbm_param_elems):
- *   [W1 (H x Q), b1 (H), W2 (H x H), b2 (H), W3 (Q x H), b3 (Q)],
- * every matrix row-major [out][in].  The network input is the node's
+ * Network (lbm_net).  LBM_NET_TANH: Q -> H -> H -> Q with tanh after the
+ * two hidden layers (H = 32 or 64).  LBM_NET_LEAKY_300_300_100: the network
+ * of the SI ("Neural Network Architecture and Optimization"), Q -> 300 ->
+ * 300 -> 100 -> Q with LeakyReLU (negative slope 0.01) after the three
+ * hidden layers.  Both have a linear output layer; the output y enters the
+ * collision as (s_out/tau) y and the whole collision update is projected
+ * off span{1, c_x, c_y[, c_z]}.  Parameters are one packed float32 vector
+ * (length lbm_param_elems), layer by layer: W_l (row-major [out][in]) then
+ * b_l, i.e. [W1 b1 W2 b2 W3 b3] for the tanh network and
+ * [W1 b1 W2 b2 W3 b3 W4 b4] for the other.  The network input is the node's
  * pre-collision deviation vector.
  */
 #ifndef LBM_H
@@ -92,6 +96,9 @@ typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 } lbm_lattice;
  *   LBM_MLP_FP16: the same with IEEE binary16 operands. */
 typedef enum { LBM_MLP_FP32 = 1, LBM_MLP_BF16 = 2, LBM_MLP_FP16 = 3 } lbm_prec;
 
+/* Network kind (see "Network" above). */
+typedef enum { LBM_NET_TANH = 0, LBM_NET_LEAKY_300_300_100 = 1 } lbm_net;
+
 /* Body force F(x), added by the exact difference method of eq. fext.
  *   LBM_FORCE_NONE.
  *   LBM_FORCE_KOLMOGOROV: F_x = amp * sin(2 pi k y / ny), F_y = F_z = 0.
@@ -109,16 +116,21 @@ typedef struct {
     int32_t force_kind;  /* lbm_force */
     int32_t force_k;     /* forcing wavenumber k */
     double force_amp;    /* forcing amplitude */
-    int32_t hidden;      /* H: 0 = plain BGK, else 32 or 64 */
+    int32_t hidden;      /* 0 = plain BGK; LBM_NET_TANH: H = 32 or 64;
+                            LBM_NET_LEAKY_300_300_100: 300 (the first width) */
     int32_t mlp_prec;    /* lbm_prec; ignored when hidden == 0 */
     double out_scale;    /* s_out: the network term is (s_out / tau) * y */
+    int32_t net;         /* lbm_net; ignored when hidden == 0 */
 } lbm_config;
 
 /* Validate `cfg` and create a context holding a copy of it, bound to the
  * current device.  The context allocates one small device buffer
  * (12 KiB per field) for the float64 partial sums of lbm_moments and
  * lbm_loss_velocity_mse; calls that use one context must therefore be
- * ordered (one stream, or synchronised streams).  Limit:
+ * ordered (one stream, or synchronised streams).  With
+ * LBM_NET_LEAKY_300_300_100 it also holds the weights in the kernel's
+ * fragment order (about 0.3 MB in bf16/fp16, 0.6 MB in fp32, refreshed from
+ * theta by every lbm_step call) and its index table (0.6 MB).  Limit:
  * batch * Q * nx * ny * nz < 2^30 elements (each population array below
  * 4 GiB, the range of the kernels' 32-bit byte offsets).  Returns
  * LBM_ERR_INVALID or LBM_ERR_UNSUPPORTED with the reason in
@@ -154,7 +166,9 @@ lbm_status lbm_init(lbm_ctx* ctx, const float* rho, const float* u, float* A0,
  * buf[(s + 1) % 2] with buf = {A, B}.  The result is therefore in B when
  * nsteps is odd and in A when it is even; for nsteps > 1 both buffers are
  * overwritten.  A != B, both population arrays.  theta: packed parameters
- * (ignored, may be null, when hidden == 0). */
+ * (ignored, may be null, when hidden == 0); with LBM_NET_LEAKY_300_300_100
+ * the call first converts theta into the context's fragment buffer, so
+ * theta may change between calls but not during one. */
 lbm_status lbm_step(lbm_ctx* ctx, float* A, float* B, const float* theta, int32_t nsteps,
                     hipStream_t stream);
 
@@ -189,7 +203,8 @@ lbm_status lbm_shift(lbm_ctx* ctx, const float* src, float* dst, int32_t directi
  * precision.  ws: device workspace of at least lbm_workspace_bytes() bytes
  * for the per-workgroup partial parameter gradients, which are summed in a
  * fixed order (the result is bit-reproducible).  dtheta may be null only
- * when hidden == 0.  lam_n must not alias lam_n1 or A_n. */
+ * when hidden == 0.  lam_n must not alias lam_n1 or A_n.  Not implemented
+ * for LBM_NET_LEAKY_300_300_100 (LBM_ERR_UNSUPPORTED). */
 lbm_status lbm_step_backward(lbm_ctx* ctx, const float* A_n, const float* theta,
                              const float* lam_n1, float* lam_n, float* dtheta, void* ws,
                              size_t ws_bytes, hipStream_t stream);

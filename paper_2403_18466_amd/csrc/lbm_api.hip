@@ -14,6 +14,9 @@
 #include "kernels_bwd.hpp"
 #include "kernels_fwd.hpp"
 #include "lbm.h"
+#include "wide.hpp"
+
+#include <vector>
 
 using namespace lbm;
 
@@ -22,6 +25,11 @@ struct lbm_ctx {
   int device;
   int ncu;
   double* partial;  // float64 reduction partials, [batch][MOM_BLOCKS][3]
+  // LBM_NET_LEAKY_300_300_100: theta -> fragment-order gather table and the
+  // packed weights it fills
+  int* wide_idx;
+  unsigned char* wide_packed;
+  int wide_nw, wide_nb;
 };
 
 namespace {
@@ -69,10 +77,72 @@ Force force_of(const lbm_config& c) {
   return f;
 }
 
-size_t param_count(int lat, int H) {
+size_t param_count(int lat, int H, int net) {
   if (H <= 0) return 0;
+  if (net == LBM_NET_LEAKY_300_300_100)
+    return lat == LBM_D2Q9 ? (size_t)WideLayout<9, P_BF16>::nparam
+                           : (size_t)WideLayout<19, P_BF16>::nparam;
   size_t Q = (size_t)lattice_q(lat), h = (size_t)H;
   return h * Q + h + h * h + h + Q * h + Q;
+}
+
+size_t param_count(const lbm_config& c) { return param_count(c.lattice, c.hidden, c.net); }
+
+// Gather table of the packed wide-network weights: entry e of the packed
+// buffer takes theta[idx[e]] (0 where idx[e] < 0).  Follows the fragment
+// layout described in wide.hpp.
+template <int Q, int P>
+std::vector<int> wide_index() {
+  using WL = WideLayout<Q, P>;
+  const int nw = WL::weight_bytes / WL::EB;
+  std::vector<int> idx((size_t)nw + WL::nbias, -1);
+  // units of tile t over K chunks [c0, c0 + kc), starting at byte offset off
+  auto emit = [&](int off, int t, int c0, int kc, auto value) {
+    for (int c = 0; c < kc; c += 2) {
+      const int nc = c + 1 < kc ? 2 : 1;
+      const int unit = off + c * WL::CHUNK;
+      for (int l = 0; l < 64; ++l)
+        for (int j = 0; j < nc; ++j)
+          for (int r = 0; r < 4; ++r) {
+            const int o = 16 * t + (l & 15), k = 16 * (c0 + c + j) + 4 * (l >> 4) + r;
+            const int e = (unit + l * nc * 4 * WL::EB + (4 * j + r) * WL::EB) / WL::EB;
+            idx[(size_t)e] = value(o, k);
+          }
+    }
+  };
+  auto v1 = [](int o, int k) {
+    if (o >= WL::N1) return -1;
+    return k < Q ? WL::oW1 + o * Q + k : (k == Q ? WL::ob1 + o : -1);
+  };
+  auto v2 = [](int o, int k) { return o < WL::N2 && k < WL::N1 ? WL::oW2 + o * WL::N1 + k : -1; };
+  auto v3 = [](int o, int k) { return o < WL::N3 && k < WL::N2 ? WL::oW3 + o * WL::N2 + k : -1; };
+  auto v4 = [](int o, int k) { return o < Q && k < WL::N3 ? WL::oW4 + o * WL::N3 + k : -1; };
+  for (int t = 0; t < WL::T1; ++t)
+    emit(WL::step_offset(t / WL::TP1) + (t % WL::TP1) * WL::K1 * WL::CHUNK, t, 0, WL::K1, v1);
+  for (int g = 0; g < WL::NG; ++g) {
+    const int off = WL::step_offset(WL::S1 + g), gt = WL::group_tiles(g);
+    for (int j = 0; j < gt; ++j)
+      emit(off + j * WL::K2 * WL::CHUNK, g * WL::RG + j, 0, WL::K2, v2);
+    for (int t3 = 0; t3 < WL::T3; ++t3)
+      emit(off + gt * WL::K2 * WL::CHUNK + t3 * gt * WL::CHUNK, t3, g * WL::RG, gt, v3);
+  }
+  for (int t4 = 0; t4 < WL::T4; ++t4)
+    emit(WL::step_offset(WL::NSTEP - 1) + t4 * WL::K4 * WL::CHUNK, t4, 0, WL::K4, v4);
+  int* b = idx.data() + nw;
+  for (int i = 0; i < 16 * WL::T2; ++i) b[WL::fb2 + i] = i < WL::N2 ? WL::ob2 + i : -1;
+  for (int i = 0; i < 16 * WL::T3; ++i) b[WL::fb3 + i] = i < WL::N3 ? WL::ob3 + i : -1;
+  for (int i = 0; i < 16 * WL::T4; ++i) b[WL::fb4 + i] = i < Q ? WL::ob4 + i : -1;
+  return idx;
+}
+
+template <int Q>
+std::vector<int> wide_index_p(int prec, int& packed_bytes) {
+  if (prec == LBM_MLP_FP32) {
+    packed_bytes = WideLayout<Q, P_F32>::packed_bytes;
+    return wide_index<Q, P_F32>();
+  }
+  packed_bytes = WideLayout<Q, P_BF16>::packed_bytes;
+  return wide_index<Q, P_BF16>();  // bf16 and fp16 share the layout
 }
 
 lbm_status validate(const lbm_config* c) {
@@ -96,8 +166,12 @@ lbm_status validate(const lbm_config* c) {
   if (c->force_kind != LBM_FORCE_NONE && !std::isfinite(c->force_amp))
     return fail(LBM_ERR_INVALID, "force_amp must be finite");
   if (c->hidden != 0) {
-    if (c->hidden != 32 && c->hidden != 64)
-      return fail(LBM_ERR_UNSUPPORTED, "hidden must be 0, 32 or 64");
+    if (c->net != LBM_NET_TANH && c->net != LBM_NET_LEAKY_300_300_100)
+      return fail(LBM_ERR_INVALID, "net must be LBM_NET_TANH or LBM_NET_LEAKY_300_300_100");
+    if (c->net == LBM_NET_TANH && c->hidden != 32 && c->hidden != 64)
+      return fail(LBM_ERR_UNSUPPORTED, "hidden must be 0, 32 or 64 for LBM_NET_TANH");
+    if (c->net == LBM_NET_LEAKY_300_300_100 && c->hidden != 300)
+      return fail(LBM_ERR_INVALID, "hidden must be 300 for LBM_NET_LEAKY_300_300_100");
     if (c->mlp_prec != LBM_MLP_FP32 && c->mlp_prec != LBM_MLP_BF16 &&
         c->mlp_prec != LBM_MLP_FP16)
       return fail(LBM_ERR_INVALID, "mlp_prec must be LBM_MLP_FP32, _BF16 or _FP16");
@@ -219,9 +293,48 @@ lbm_status launch_nlbm_p(lbm_ctx* ctx, const float* Ain, float* Aout, const floa
   }
 }
 
+// The wide network: weights into fragment order, then the persistent step.
+template <class L, int P>
+lbm_status wide_pack(lbm_ctx* ctx, const float* theta, hipStream_t s) {
+  const int n = ctx->wide_nw + ctx->wide_nb;
+  hipLaunchKernelGGL(wide_pack_kernel<P>, dim3(blocks_for(n)), dim3(256), 0, s, theta,
+                     ctx->wide_idx, ctx->wide_packed, ctx->wide_nw, ctx->wide_nb);
+  LBM_LAUNCHED("wide_pack_kernel");
+  return LBM_OK;
+}
+
+template <class L, int P>
+lbm_status launch_wide(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t s) {
+  using C = WideCfg<L, P>;
+  Grid G = grid_of(ctx->cfg);
+  int nxc = (G.nx + 63) / 64;
+  long long nitems = (long long)nxc * G.ny * G.nz * G.batch;
+  if (nitems >= (1LL << 31)) return fail(LBM_ERR_INVALID, "too many work items");
+  // one workgroup of 8 wavefronts per compute unit (the LDS holds one)
+  long long nb = ctx->ncu;
+  long long cap = (nitems + C::WAVES - 1) / C::WAVES;
+  if (nb > cap) nb = cap;
+  if (nb >= 16) nb -= nb % 8;
+  const long long per = (nitems + nb * C::WAVES - 1) / (nb * C::WAVES);
+  const lbm_config& c = ctx->cfg;
+  hipLaunchKernelGGL((wide_step_kernel<L, P>), dim3((unsigned)nb), dim3(C::THREADS), 0, s, Ain,
+                     Aout, ctx->wide_packed, G, force_of(c), (float)c.rho0,
+                     (float)(1.0 / c.tau), (float)(c.out_scale / c.tau), (int)per, (int)nitems,
+                     nxc);
+  LBM_LAUNCHED("wide_step_kernel");
+  return LBM_OK;
+}
+
 template <class L>
 lbm_status one_step(lbm_ctx* ctx, const float* Ain, float* Aout, const float* theta,
                     hipStream_t s) {
+  if (ctx->cfg.net == LBM_NET_LEAKY_300_300_100 && ctx->cfg.hidden != 0) {
+    switch (ctx->cfg.mlp_prec) {
+      case LBM_MLP_FP32: return launch_wide<L, P_F32>(ctx, Ain, Aout, s);
+      case LBM_MLP_BF16: return launch_wide<L, P_BF16>(ctx, Ain, Aout, s);
+      default: return launch_wide<L, P_F16>(ctx, Ain, Aout, s);
+    }
+  }
   switch (ctx->cfg.hidden) {
     case 0: return launch_bgk<L>(ctx, Ain, Aout, s);
     case 32: return launch_nlbm_p<L, 32>(ctx, Ain, Aout, theta, s);
@@ -238,7 +351,7 @@ lbm_status launch_bwd(lbm_ctx* ctx, const float* A, const float* theta, const fl
   long long nitems = (long long)nxc * G.ny * G.nz * G.batch;
   if (nitems >= (1LL << 31)) return fail(LBM_ERR_INVALID, "too many work items");
   const lbm_config& c = ctx->cfg;
-  const int nparam = (int)param_count(c.lattice, c.hidden);
+  const int nparam = (int)param_count(c);
   float* part = static_cast<float*>(ws);
   const unsigned blocks = bwd_blocks(ctx->ncu);
   hipLaunchKernelGGL((nlbm_backward_kernel<L, H, P>), dim3(blocks), dim3(256), 0, s, A, theta,
@@ -326,12 +439,37 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   ctx->device = dev;
   ctx->ncu = prop.multiProcessorCount;
   ctx->partial = nullptr;
+  ctx->wide_idx = nullptr;
+  ctx->wide_packed = nullptr;
+  ctx->wide_nw = ctx->wide_nb = 0;
   size_t bytes = sizeof(double) * 3 * MOM_BLOCKS * (size_t)cfg->batch;
   hipError_t e = hipMalloc(&ctx->partial, bytes);
   if (e != hipSuccess) {
     delete ctx;
     return fail(LBM_ERR_HIP, std::string("hipMalloc of the reduction buffer: ") +
                                  hipGetErrorString(e));
+  }
+  if (cfg->hidden != 0 && cfg->net == LBM_NET_LEAKY_300_300_100) {
+    int pbytes = 0;
+    std::vector<int> idx = cfg->lattice == LBM_D2Q9 ? wide_index_p<9>(cfg->mlp_prec, pbytes)
+                                                     : wide_index_p<19>(cfg->mlp_prec, pbytes);
+    const int eb = cfg->mlp_prec == LBM_MLP_FP32 ? 4 : 2;
+    ctx->wide_nb = cfg->lattice == LBM_D2Q9 ? WideLayout<9, P_BF16>::nbias
+                                            : WideLayout<19, P_BF16>::nbias;
+    ctx->wide_nw = (int)idx.size() - ctx->wide_nb;
+    if ((long long)ctx->wide_nw * eb + 4LL * ctx->wide_nb != pbytes) {
+      lbm_destroy(ctx);
+      return fail(LBM_ERR_HIP, "internal error: wide-network layout size mismatch");
+    }
+    e = hipMalloc(&ctx->wide_idx, sizeof(int) * idx.size());
+    if (e == hipSuccess) e = hipMalloc(&ctx->wide_packed, (size_t)pbytes);
+    if (e == hipSuccess)
+      e = hipMemcpy(ctx->wide_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      lbm_destroy(ctx);
+      return fail(LBM_ERR_HIP, std::string("allocation of the wide-network buffers: ") +
+                                   hipGetErrorString(e));
+    }
   }
   *out = ctx;
   return LBM_OK;
@@ -342,6 +480,8 @@ lbm_status lbm_destroy(lbm_ctx* ctx) {
   LBM_GUARD_BEGIN
   if (!ctx) return LBM_OK;
   if (ctx->partial) (void)hipFree(ctx->partial);
+  if (ctx->wide_idx) (void)hipFree(ctx->wide_idx);
+  if (ctx->wide_packed) (void)hipFree(ctx->wide_packed);
   delete ctx;
   return LBM_OK;
   LBM_GUARD_END
@@ -355,13 +495,12 @@ size_t lbm_state_elems(const lbm_ctx* ctx) {
 
 size_t lbm_param_elems(const lbm_ctx* ctx) {
   if (!ctx) return 0;
-  return param_count(ctx->cfg.lattice, ctx->cfg.hidden);
+  return param_count(ctx->cfg);
 }
 
 size_t lbm_workspace_bytes(const lbm_ctx* ctx) {
-  if (!ctx || ctx->cfg.hidden == 0) return 0;
-  return sizeof(float) * (size_t)bwd_blocks(ctx->ncu) *
-         param_count(ctx->cfg.lattice, ctx->cfg.hidden);
+  if (!ctx || ctx->cfg.hidden == 0 || ctx->cfg.net != LBM_NET_TANH) return 0;
+  return sizeof(float) * (size_t)bwd_blocks(ctx->ncu) * param_count(ctx->cfg);
 }
 
 lbm_status lbm_lattice_tables(int32_t lattice, int32_t* q, int32_t* c, double* w) {
@@ -411,6 +550,20 @@ lbm_status lbm_step(lbm_ctx* ctx, float* A, float* B, const float* theta, int32_
   if (A == B) return fail(LBM_ERR_INVALID, "A and B must be different buffers");
   if (nsteps < 1) return fail(LBM_ERR_INVALID, "nsteps must be >= 1");
   if (ctx->cfg.hidden != 0 && !theta) return fail(LBM_ERR_INVALID, "theta is null");
+  if (ctx->cfg.hidden != 0 && ctx->cfg.net == LBM_NET_LEAKY_300_300_100) {
+    const bool d2 = ctx->cfg.lattice == LBM_D2Q9;
+    switch (ctx->cfg.mlp_prec) {
+      case LBM_MLP_FP32:
+        st = d2 ? wide_pack<D2Q9, P_F32>(ctx, theta, stream) : wide_pack<D3Q19, P_F32>(ctx, theta, stream);
+        break;
+      case LBM_MLP_BF16:
+        st = d2 ? wide_pack<D2Q9, P_BF16>(ctx, theta, stream) : wide_pack<D3Q19, P_BF16>(ctx, theta, stream);
+        break;
+      default:
+        st = d2 ? wide_pack<D2Q9, P_F16>(ctx, theta, stream) : wide_pack<D3Q19, P_F16>(ctx, theta, stream);
+    }
+    if (st != LBM_OK) return st;
+  }
   float* buf[2] = {A, B};
   for (int s = 0; s < nsteps; ++s) {
     const float* in = buf[s & 1];
@@ -456,6 +609,8 @@ lbm_status lbm_step_backward(lbm_ctx* ctx, const float* A_n, const float* theta,
   if (!A_n || !lam_n1 || !lam_n) return fail(LBM_ERR_INVALID, "null array");
   if (lam_n == lam_n1 || lam_n == A_n)
     return fail(LBM_ERR_INVALID, "lam_n must not alias lam_n1 or A_n");
+  if (ctx->cfg.hidden != 0 && ctx->cfg.net != LBM_NET_TANH)
+    return fail(LBM_ERR_UNSUPPORTED, "the adjoint of LBM_NET_LEAKY_300_300_100 is not implemented");
   if (ctx->cfg.hidden != 0) {
     if (!theta || !dtheta) return fail(LBM_ERR_INVALID, "theta and dtheta must be given");
     if (!ws) return fail(LBM_ERR_INVALID, "workspace is null");

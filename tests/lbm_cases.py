@@ -45,7 +45,7 @@ def lib_config(ocfg, prec="fp32"):
                       batch=ocfg.batch, tau=ocfg.tau, rho0=ocfg.rho0,
                       force_kind=ocfg.force_kind, force_k=ocfg.force_k,
                       force_amp=ocfg.force_amp, hidden=ocfg.hidden, mlp_prec=prec,
-                      out_scale=ocfg.out_scale)
+                      out_scale=ocfg.out_scale, net=ocfg.net)
 
 
 def fourier_state(ocfg, umax=0.05, seed=0, kmax=4):
