@@ -59,6 +59,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-train", action="store_true", help="skip the training-step timing")
     p.add_argument("--no-d3q19", action="store_true", help="skip the D3Q19 256^3 timing")
+    p.add_argument("--no-wide", action="store_true",
+                   help="skip the D3Q19 256^3 timing of the 19-300-300-100-19 network")
     p.add_argument("--variants", default="bf16,fp16,fp32,bgk")
     return p.parse_args()
 
@@ -200,6 +202,56 @@ def time_d3q19(torch, lbm, inputs, steps):
     return res
 
 
+# multiply-add flops of the 19 -> 300 -> 300 -> 100 -> 19 network per node
+WIDE_FLOP_PER_LUP = 2 * (19 * 300 + 300 * 300 + 300 * 100 + 100 * 19)
+MFMA_PEAK = {"bf16": 2.5e15, "fp16": 2.5e15}  # dense, MI355X
+
+
+def time_wide(torch, lbm, inputs, steps):
+    """The SI's collision network, 19 -> 300 -> 300 -> 100 -> 19 with
+    LeakyReLU, on D3Q19 256^3 (tau 0.51, s_out 2^-6, Glorot weights from seed
+    1, the same solenoidal initial field as the 3-D workload), bf16 and fp16
+    matrix cores.  This path is bound by the matrix cores: the roofline is
+    the network's algorithmic flops against the dense peak."""
+    n = 256
+    u = inputs.solenoidal_spectrum_velocity((n, n, n), 4.0, 0.04, seed=0).astype("float32")
+    ud = torch.from_numpy(u).reshape(1, 3, n, n, n).cuda()
+    del u
+    theta = torch.from_numpy(inputs.glorot_params_net(inputs.net_widths(19, 0, "paper"), 1)).cuda()
+    res = {}
+    for prec in ("bf16", "fp16"):
+        cfg = lbm.Config(lattice="D3Q19", nx=n, ny=n, nz=n, tau=TAU, hidden=300, net="paper",
+                         mlp_prec=prec, out_scale=S_OUT)
+        L = lbm.Lattice(cfg)
+        A = L.init(torch.ones((1, n, n, n), device="cuda"), ud)
+        B = torch.empty_like(A)
+        lbm.lbm_step(L.ctx, cfg, A, B, theta, 2)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = lbm.lbm_step(L.ctx, cfg, A, B, theta, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        _, _, diag = L.moments(out, want_fields=False)
+        lups = n ** 3 / (ms * 1e-3)
+        flops = WIDE_FLOP_PER_LUP * lups
+        res[prec] = {"ms_per_step": ms, "mlups": lups / 1e6, "nonfinite": int(diag[0, 2].item()),
+                     "roofline": {"bound": "mfma", "achieved": flops / 1e12,
+                                  "peak": MFMA_PEAK[prec] / 1e12, "unit": "TFLOP/s",
+                                  "frac": flops / MFMA_PEAK[prec],
+                                  "hbm_frac": 152 * lups / HBM_PEAK}}
+        del A, B
+        L.close()
+        print(f"# wide network D3Q19 256^3 {prec}: {lups / 1e6:.0f} MLUPS, "
+              f"{flops / 1e12:.0f} TFLOP/s", file=sys.stderr, flush=True)
+    res["workload"] = ("D3Q19 256^3, collision network 19-300-300-100-19 LeakyReLU (the SI's), "
+                       "tau 0.51, s_out 2^-6, weights streamed through LDS, includes the "
+                       "per-call weight packing")
+    return res
+
+
 def cpu_baseline():
     """The FP64 oracle on a bounded sample of the same workload: one step of
     the same network on a 1024 x 1024 field (serial C, one host thread)."""
@@ -310,6 +362,8 @@ def main():
                                   HBM_PEAK}
     if not args.no_d3q19:
         result["d3q19_256"] = time_d3q19(torch, lbm, inputs, max(10, args.steps // 10))
+    if not args.no_wide:
+        result["wide_d3q19_256"] = time_wide(torch, lbm, inputs, max(10, args.steps // 10))
     if not args.no_train:
         tr = {p: time_training(torch, lbm, inputs, p, 5) for p in ("bf16", "fp32")}
         for p, v in tr.items():

@@ -14,7 +14,15 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm_hip.so")
-SOURCES = [os.path.join(CSRC, "lbm_api.hip")]
+# (source, extra flags): the wide-network kernels use the max-ILP instruction
+# scheduler, which keeps their LDS weight reads ahead of the matrix-core work,
+SOURCES = [
+    (os.path.join(CSRC, "lbm_api.hip"), ()),
+    # and IEEE mode off (LeakyReLU's max then needs no NaN-quieting
+    # canonicalisation; the wide step has no NaN tests)
+    (os.path.join(CSRC, "wide.hip"), ("-mllvm", "-amdgpu-sched-strategy=max-ilp",
+                                      "-mno-amdgpu-ieee", "-fno-honor-nans")),
+]
 
 
 def hipcc() -> str:
@@ -24,9 +32,9 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build the library)")
 
 
-def command(out: str = LIB, extra=()):
+def compile_command(src: str, obj: str, extra=()):
     return [
-        hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+        hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-c",
         # no packed FP32 instructions anywhere in the device code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         # matrix-core results in VGPRs, read by the activation without
@@ -34,18 +42,28 @@ def command(out: str = LIB, extra=()):
         "-mllvm", "-amdgpu-mfma-vgpr-form",
         "-Wno-unused-command-line-argument",
         "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-        *extra, *SOURCES, "-o", out,
+        *extra, src, "-o", obj,
     ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = command(tmp)
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+
+
+def build(verbose: bool = False) -> str:
+    objs = []
+    for src, extra in SOURCES:
+        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
+        _run(compile_command(src, obj, extra), verbose)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+    for obj in objs:
+        os.remove(obj)
     os.replace(tmp, LIB)
     return LIB
 

@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void moments_kernel(const float* __restrict__ 
 }
 
 // One block of 256 threads per field; partial: [batch][nblk][3].
-__global__ __launch_bounds__(256) void diag_reduce_kernel(const double* __restrict__ partial,
+static __global__ __launch_bounds__(256) void diag_reduce_kernel(const double* __restrict__ partial,
                                                           double* __restrict__ diag, int nblk) {
   const int b = blockIdx.x;
   __shared__ double red[3][256];

@@ -294,12 +294,16 @@ lbm_status launch_nlbm_p(lbm_ctx* ctx, const float* Ain, float* Aout, const floa
 }
 
 // The wide network: weights into fragment order, then the persistent step.
-template <class L, int P>
+int prec_of(int mlp_prec) {
+  return mlp_prec == LBM_MLP_FP32 ? P_F32 : (mlp_prec == LBM_MLP_BF16 ? P_BF16 : P_F16);
+}
+
 lbm_status wide_pack(lbm_ctx* ctx, const float* theta, hipStream_t s) {
   const int n = ctx->wide_nw + ctx->wide_nb;
-  hipLaunchKernelGGL(wide_pack_kernel<P>, dim3(blocks_for(n)), dim3(256), 0, s, theta,
-                     ctx->wide_idx, ctx->wide_packed, ctx->wide_nw, ctx->wide_nb);
-  LBM_LAUNCHED("wide_pack_kernel");
+  hipError_t e = wide_pack_launch(prec_of(ctx->cfg.mlp_prec), blocks_for(n), s, theta,
+                                  ctx->wide_idx, ctx->wide_packed, ctx->wide_nw, ctx->wide_nb);
+  if (e != hipSuccess)
+    return fail(LBM_ERR_HIP, std::string("launch of wide_pack_kernel: ") + hipGetErrorString(e));
   return LBM_OK;
 }
 
@@ -317,11 +321,11 @@ lbm_status launch_wide(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t 
   if (nb >= 16) nb -= nb % 8;
   const long long per = (nitems + nb * C::WAVES - 1) / (nb * C::WAVES);
   const lbm_config& c = ctx->cfg;
-  hipLaunchKernelGGL((wide_step_kernel<L, P>), dim3((unsigned)nb), dim3(C::THREADS), 0, s, Ain,
-                     Aout, ctx->wide_packed, G, force_of(c), (float)c.rho0,
-                     (float)(1.0 / c.tau), (float)(c.out_scale / c.tau), (int)per, (int)nitems,
-                     nxc);
-  LBM_LAUNCHED("wide_step_kernel");
+  hipError_t e = wide_step_launch(L::Q == 19, P, (unsigned)nb, s, Ain, Aout, ctx->wide_packed, G,
+                                  force_of(c), (float)c.rho0, (float)(1.0 / c.tau),
+                                  (float)(c.out_scale / c.tau), (int)per, (int)nitems, nxc);
+  if (e != hipSuccess)
+    return fail(LBM_ERR_HIP, std::string("launch of wide_step_kernel: ") + hipGetErrorString(e));
   return LBM_OK;
 }
 
@@ -551,17 +555,7 @@ lbm_status lbm_step(lbm_ctx* ctx, float* A, float* B, const float* theta, int32_
   if (nsteps < 1) return fail(LBM_ERR_INVALID, "nsteps must be >= 1");
   if (ctx->cfg.hidden != 0 && !theta) return fail(LBM_ERR_INVALID, "theta is null");
   if (ctx->cfg.hidden != 0 && ctx->cfg.net == LBM_NET_LEAKY_300_300_100) {
-    const bool d2 = ctx->cfg.lattice == LBM_D2Q9;
-    switch (ctx->cfg.mlp_prec) {
-      case LBM_MLP_FP32:
-        st = d2 ? wide_pack<D2Q9, P_F32>(ctx, theta, stream) : wide_pack<D3Q19, P_F32>(ctx, theta, stream);
-        break;
-      case LBM_MLP_BF16:
-        st = d2 ? wide_pack<D2Q9, P_BF16>(ctx, theta, stream) : wide_pack<D3Q19, P_BF16>(ctx, theta, stream);
-        break;
-      default:
-        st = d2 ? wide_pack<D2Q9, P_F16>(ctx, theta, stream) : wide_pack<D3Q19, P_F16>(ctx, theta, stream);
-    }
+    st = wide_pack(ctx, theta, stream);
     if (st != LBM_OK) return st;
   }
   float* buf[2] = {A, B};

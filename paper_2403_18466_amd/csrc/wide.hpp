@@ -176,6 +176,119 @@ __device__ inline void tile_row(const unsigned char* p, int lane, f4 (&acc)[NT],
   }
 }
 
+// acc[j][n] += W(tile j) x[n] for the GT tiles whose units start at
+// p + j * KC * CHUNK, over K chunks 0..KC-1: the fragments of the next chunk
+// pair of every tile are read from LDS before the MFMAs of the current pair
+// are issued, so LDS latency overlaps matrix-core work.
+template <int P, int KC, int NT, int GT>
+__device__ inline void tiles_row(const unsigned char* p, int lane, f4 (&acc)[GT][NT],
+                                 const typename Frag<P>::T (*x)[NT]) {
+  using Fr = typename Frag<P>::T;
+  constexpr int CH = WideLayout<9, P>::CHUNK;
+  constexpr int NP = KC / 2;
+  Fr a0[GT], a1[GT];
+  if constexpr (NP > 0) {
+#pragma unroll
+    for (int j = 0; j < GT; ++j) lds_pair<P>(p + j * KC * CH, lane, a0[j], a1[j]);
+  }
+  Fr s[GT];
+  if constexpr (KC % 2 == 1) {
+#pragma unroll
+    for (int j = 0; j < GT; ++j) s[j] = lds_single<P>(p + j * KC * CH + (KC - 1) * CH, lane);
+  }
+#pragma unroll
+  for (int c = 0; c < NP; ++c) {
+    Fr b0[GT], b1[GT];
+    if (c + 1 < NP) {
+#pragma unroll
+      for (int j = 0; j < GT; ++j)
+        lds_pair<P>(p + j * KC * CH + (2 * c + 2) * CH, lane, b0[j], b1[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < GT; ++j)
+#pragma unroll
+      for (int n = 0; n < NT; ++n)
+        acc[j][n] = mma_pair<P>(acc[j][n], a0[j], a1[j], x[2 * c][n], x[2 * c + 1][n]);
+    if (c + 1 < NP) {
+#pragma unroll
+      for (int j = 0; j < GT; ++j) {
+        a0[j] = b0[j];
+        a1[j] = b1[j];
+      }
+    }
+  }
+  if constexpr (KC % 2 == 1) {
+#pragma unroll
+    for (int j = 0; j < GT; ++j)
+#pragma unroll
+      for (int n = 0; n < NT; ++n) acc[j][n] = mma_chunk<P>(acc[j][n], s[j], x[KC - 1][n]);
+  }
+}
+
+// Body force at integer node (x, y, z) in float32: the argument 2 pi k y / n
+// is reduced exactly in integers, then sin(pi t) with t in [0, 2) (error a
+// few 1e-7 of the amplitude).
+__device__ inline float sin_frac_f(long long num, int den) {
+  long long r = num % den;
+  if (r < 0) r += den;
+  return sinpif((float)(2 * r) / (float)den);
+}
+
+__device__ inline void body_force_f(const Force& f, const Grid& G, int x, int y, int z,
+                                    float F[3]) {
+  F[0] = F[1] = F[2] = 0.f;
+  if (f.kind == 1) {
+    F[0] = f.amp * sin_frac_f((long long)f.k * y, G.ny);
+  } else if (f.kind == 2) {
+    F[0] = f.amp * sin_frac_f((long long)f.k * y, G.ny);
+    F[1] = f.amp * sin_frac_f((long long)f.k * z, G.nz);
+    F[2] = f.amp * sin_frac_f((long long)f.k * x, G.nx);
+  }
+}
+
+// Wave-uniform byte offsets of the rows one 64-node item reads and writes:
+// the start of field b, the plane stride, and the rows y - c_y, z - c_z for
+// c in {-1, 0, 1} (periodic); every population's row is a sum of these.
+struct RowOffsets {
+  unsigned field, plane;
+  unsigned yo[3], zo[3];  // index c + 1
+};
+
+__device__ inline RowOffsets row_offsets(const Grid& G, int Q, int b, int y, int z) {
+  RowOffsets r;
+  b = __builtin_amdgcn_readfirstlane(b);
+  y = __builtin_amdgcn_readfirstlane(y);
+  z = __builtin_amdgcn_readfirstlane(z);
+  const unsigned rowb = (unsigned)G.nx * 4u;
+  r.plane = (unsigned)G.plane * 4u;
+  r.field = (unsigned)(b * Q) * r.plane;
+#pragma unroll
+  for (int c = -1; c <= 1; ++c) {
+    r.yo[c + 1] = (unsigned)wrap_sub(y, c, G.ny) * rowb;
+    r.zo[c + 1] = (unsigned)wrap_sub(z, c, G.nz) * rowb * (unsigned)G.ny;
+  }
+  return r;
+}
+
+// g_q = A_q(x - c_q) for this lane's node.
+template <class L, int q = 0>
+__device__ inline void gather_rows(rsrc_t src, const RowOffsets& r, const Item& t, float g[L::Q]) {
+  if constexpr (q < L::Q) {
+    const unsigned so = r.field + q * r.plane + r.zo[L::cz[q] + 1] + r.yo[L::cy[q] + 1];
+    const int vo = L::cx[q] > 0 ? t.vm : (L::cx[q] < 0 ? t.vp : t.vx);
+    g[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src, vo, (int)so, 0));
+    gather_rows<L, q + 1>(src, r, t, g);
+  }
+}
+
+template <class L>
+__device__ inline void store_rows(rsrc_t dst, const RowOffsets& r, const Item& t, const float v[L::Q]) {
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v[q]), dst, t.vx,
+                                          (int)(r.field + q * r.plane + r.zo[1] + r.yo[1]), 0);
+}
+
 template <class L, int P>
 struct WideCfg {
   using WL = WideLayout<L::Q, P>;
@@ -249,7 +362,10 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
   ItemWalk cur, nxt;
   cur.start(it0 < nitems ? it0 : nitems - 1, nxc, G);
   float gn[Q];
-  if (it0 < nitems) gather_item<L>(src, G, cur.item(G, lane), gn);
+  if (it0 < nitems) {
+    const Item t0 = cur.item(G, lane);
+    gather_rows<L>(src, row_offsets(G, Q, t0.b, t0.y, t0.z), t0, gn);
+  }
 
   constexpr int YC = C::YC;
   int parity = 0;  // LDS buffer holding the current step
@@ -265,8 +381,9 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
     nxt = cur;
     nxt.next(nxc, G);
 
-    for (int sw = 0; sw < NS; ++sw) {
-      const int row0 = sw * 16 * NT;
+    static_for<NS>([&](auto swc) {
+      constexpr int sw = decltype(swc)::value;
+      constexpr int row0 = sw * 16 * NT;
       F x[WL::K1][NT];
       F h1[WL::T1][NT];
       f4 acc3[WL::T3][NT];
@@ -274,7 +391,12 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
         constexpr int s = decltype(sc)::value;
         constexpr int sn = (s + 1) % WL::NSTEP;
         stage_issue(WL::step_offset(sn), WL::step_bytes(sn));
-        if (s == 1 && sw == NS - 1 && more) gather_item<L>(src, G, nxt.item(G, lane), gn);
+        if constexpr (s == 1 && sw == NS - 1) {
+          if (more) {
+            const Item tn = nxt.item(G, lane);
+            gather_rows<L>(src, row_offsets(G, Q, tn.b, tn.y, tn.z), tn, gn);
+          }
+        }
         const unsigned char* S = stage + parity * SB;
         if constexpr (s < WL::S1) {
           // layer 1: h1 = leaky(W1 [g, 1]); input columns past YC are zero
@@ -315,19 +437,20 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
           constexpr int g = s - WL::S1;
           constexpr int GT = WL::group_tiles(g);
           F h2[WL::RG][NT];
-          static_for<GT>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            {
-              constexpr int tt = g * WL::RG + j;
-              f4 acc[NT];
-              const f4 b = *reinterpret_cast<const f4*>(bias + WL::fb2 + 16 * tt + 4 * lg);
+          {
+            f4 acc[GT][NT];
 #pragma unroll
-              for (int n = 0; n < NT; ++n) acc[n] = b;
-              tile_row<P, WL::K2, NT>(S + j * WL::K2 * CH, lane, acc, h1);
+            for (int j = 0; j < GT; ++j) {
+              const f4 b = *reinterpret_cast<const f4*>(bias + WL::fb2 + 16 * (g * WL::RG + j) + 4 * lg);
 #pragma unroll
-              for (int n = 0; n < NT; ++n) h2[j][n] = to_frag<P>(leaky4(acc[n]));
+              for (int n = 0; n < NT; ++n) acc[j][n] = b;
             }
-          });
+            tiles_row<P, WL::K2, NT, GT>(S, lane, acc, h1);
+#pragma unroll
+            for (int j = 0; j < GT; ++j)
+#pragma unroll
+              for (int n = 0; n < NT; ++n) h2[j][n] = to_frag<P>(leaky4(acc[j][n]));
+          }
           const unsigned char* S3 = S + GT * WL::K2 * CH;
 #pragma unroll
           for (int t3 = 0; t3 < WL::T3; ++t3) {
@@ -369,7 +492,7 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
         parity ^= 1;
         __syncthreads();
       });
-    }
+    });
 
     // item end (node layout): BGK, network term, projection, force, store
     {
@@ -381,14 +504,21 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
 #pragma unroll
       for (int q = 0; q < Q; ++q) upd[q] = __builtin_fmaf(knn, T[lane * SX + YC + q], upd[q]);
       float F3[3] = {0.f, 0.f, 0.f};
-      if (Fc.kind != 0) body_force(Fc, G, t.x, t.y, t.z, F3);
+      if (Fc.kind != 0) body_force_f(Fc, G, t.x, t.y, t.z, F3);
       float post[Q];
       finish_collision<L>(g, upd, rho, u, F3, Fc.kind != 0, post);
-      if (valid && t.active) store_local<L>(dst, G, t, post);
+      if (valid && t.active) store_rows<L>(dst, row_offsets(G, Q, t.b, t.y, t.z), t, post);
     }
     wave_lds_sync();
     cur = nxt;
   }
 }
+
+// Launches, defined in wide.hip (prec: a Prec value).
+hipError_t wide_step_launch(bool d3q19, int prec, unsigned nb, hipStream_t s, const float* Ain,
+                            float* Aout, const unsigned char* packed, Grid G, Force Fc,
+                            float rho0, float omega, float knn, int per, int nitems, int nxc);
+hipError_t wide_pack_launch(int prec, unsigned blocks, hipStream_t s, const float* theta,
+                            const int* idx, unsigned char* packed, int nw, int nb);
 
 }  // namespace lbm
