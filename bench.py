@@ -61,7 +61,7 @@ def parse():
     p.add_argument("--no-d3q19", action="store_true", help="skip the D3Q19 256^3 timing")
     p.add_argument("--no-wide", action="store_true",
                    help="skip the D3Q19 256^3 timing of the 19-300-300-100-19 network")
-    p.add_argument("--variants", default="bf16,fp16,fp32,bgk")
+    p.add_argument("--variants", default="bf16,fp16,fp32,bgk,smag")
     return p.parse_args()
 
 
@@ -72,8 +72,12 @@ def make_state(torch, lbm, inputs, L):
     return L.init(rho, ud)
 
 
-def time_variant(torch, lbm, inputs, prec, hidden, steps, warmup, A0):
-    cfg = lbm.Config(nx=N, ny=N, tau=TAU, hidden=hidden, mlp_prec=prec, out_scale=S_OUT)
+SMAG_CS = 0.17  # Smagorinsky constant of the comparison collision
+
+
+def time_variant(torch, lbm, inputs, prec, hidden, steps, warmup, A0, collision="bgk"):
+    cfg = lbm.Config(nx=N, ny=N, tau=TAU, hidden=hidden, mlp_prec=prec, out_scale=S_OUT,
+                     collision=collision, smag_cs=SMAG_CS if collision == "smagorinsky" else 0.0)
     L = lbm.Lattice(cfg)
     theta = None
     if hidden:
@@ -161,9 +165,11 @@ def time_d3q19(torch, lbm, inputs, steps):
     ud = torch.from_numpy(u).reshape(1, 3, n, n, n).cuda()
     del u
     res = {}
-    for name, hidden in (("bf16", HIDDEN), ("bgk", 0)):
+    for name, hidden, coll in (("bf16", HIDDEN, "bgk"), ("bgk", 0, "bgk"),
+                               ("smag", 0, "smagorinsky")):
         cfg = lbm.Config(lattice="D3Q19", nx=n, ny=n, nz=n, tau=TAU, hidden=hidden,
-                         mlp_prec="bf16", out_scale=S_OUT)
+                         mlp_prec="bf16", out_scale=S_OUT, collision=coll,
+                         smag_cs=SMAG_CS if coll == "smagorinsky" else 0.0)
         L = lbm.Lattice(cfg)
         A = L.init(torch.ones((1, n, n, n), device="cuda"), ud)
         B = torch.empty_like(A)
@@ -299,12 +305,14 @@ def main():
 
     variants = {}
     wanted = args.variants.split(",")
-    table = {"bf16": ("bf16", HIDDEN), "fp16": ("fp16", HIDDEN), "fp32": ("fp32", HIDDEN),
-             "bgk": ("fp32", 0)}
+    table = {"bf16": ("bf16", HIDDEN, "bgk"), "fp16": ("fp16", HIDDEN, "bgk"),
+             "fp32": ("fp32", HIDDEN, "bgk"), "bgk": ("fp32", 0, "bgk"),
+             "smag": ("fp32", 0, "smagorinsky")}
     for name in ["bf16"] + [v for v in wanted if v != "bf16"]:
-        prec, hidden = table[name]
+        prec, hidden, coll = table[name]
         steps = args.steps if name != "fp32" else max(1, args.steps // 2)
-        variants[name] = time_variant(torch, lbm, inputs, prec, hidden, steps, args.warmup, A0)
+        variants[name] = time_variant(torch, lbm, inputs, prec, hidden, steps, args.warmup, A0,
+                                      coll)
         print(f"# {name}: {variants[name]['ms_per_step']:.4f} ms/step, "
               f"{variants[name]['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
 
@@ -360,6 +368,13 @@ def main():
                                   "unit": "GB/s",
                                   "frac": BYTES_PER_LUP * N * N / (bgk["ms_per_step"] * 1e-3) /
                                   HBM_PEAK}
+    smag = variants.get("smag")
+    if smag:
+        result["smagorinsky_roofline"] = {
+            "bound": "hbm", "achieved": BYTES_PER_LUP * N * N / (smag["ms_per_step"] * 1e-3) / 1e9,
+            "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": BYTES_PER_LUP * N * N / (smag["ms_per_step"] * 1e-3) / HBM_PEAK,
+            "collision": f"Smagorinsky LES, C_s = {SMAG_CS}, tau 0.51, same field"}
     if not args.no_d3q19:
         result["d3q19_256"] = time_d3q19(torch, lbm, inputs, max(10, args.steps // 10))
     if not args.no_wide:

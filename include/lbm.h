@@ -99,6 +99,20 @@ typedef enum { LBM_MLP_FP32 = 1, LBM_MLP_BF16 = 2, LBM_MLP_FP16 = 3 } lbm_prec;
 /* Network kind (see "Network" above). */
 typedef enum { LBM_NET_TANH = 0, LBM_NET_LEAKY_300_300_100 = 1 } lbm_net;
 
+/* Collision operator.
+ *   LBM_COLLISION_BGK: BGK at tau (eq. bgk-sm), plus the network if hidden > 0.
+ *   LBM_COLLISION_SMAGORINSKY: BGK at the local relaxation time of the
+ *     Smagorinsky model (SI, "Implementing the Smagorinsky Turbulence Model
+ *     in LBM"), computed from the node's non-equilibrium stress in the same
+ *     pass, with dt = 1, c_s^2 = 1/3 and filter width 1:
+ *       Pi^neq_ab = sum_q c_qa c_qb (f_q - f^eq_q),
+ *       S_ab = -3 / (2 tau) Pi^neq_ab,  |S| = sqrt(2 S_ab S_ab),
+ *       tau_eff = 3 ((tau - 1/2) / 3 + smag_cs^2 |S|) + 1/2.
+ *     The SI prints the factor as 3 tau / 2; 3 / (2 tau) is the
+ *     Chapman-Enskog relation Pi^neq = -2 rho c_s^2 tau S with rho = 1.
+ *     Requires hidden == 0; no adjoint (LBM_ERR_UNSUPPORTED). */
+typedef enum { LBM_COLLISION_BGK = 0, LBM_COLLISION_SMAGORINSKY = 1 } lbm_collision;
+
 /* Body force F(x), added by the exact difference method of eq. fext.
  *   LBM_FORCE_NONE.
  *   LBM_FORCE_KOLMOGOROV: F_x = amp * sin(2 pi k y / ny), F_y = F_z = 0.
@@ -121,6 +135,8 @@ typedef struct {
     int32_t mlp_prec;    /* lbm_prec; ignored when hidden == 0 */
     double out_scale;    /* s_out: the network term is (s_out / tau) * y */
     int32_t net;         /* lbm_net; ignored when hidden == 0 */
+    int32_t collision;   /* lbm_collision */
+    double smag_cs;      /* Smagorinsky constant C_s (LBM_COLLISION_SMAGORINSKY), >= 0 */
 } lbm_config;
 
 /* Validate `cfg` and create a context holding a copy of it, bound to the

@@ -29,6 +29,7 @@ _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 LATTICES = {"D2Q9": 0, "D3Q19": 1}
 QUANT = {"none": 0, "bf16": 1, "fp16": 2}
 NETS = {"tanh": 0, "paper": 1}
+COLLISIONS = {"bgk": 0, "smagorinsky": 1}
 
 
 def build(force: bool = False) -> str:
@@ -50,7 +51,7 @@ class _Cfg(ctypes.Structure):
         ("force_kind", ctypes.c_int32), ("force_amp", ctypes.c_double),
         ("force_k", ctypes.c_int32), ("hidden", ctypes.c_int32),
         ("quant", ctypes.c_int32), ("out_scale", ctypes.c_double),
-        ("net", ctypes.c_int32),
+        ("net", ctypes.c_int32), ("collision", ctypes.c_int32), ("smag_cs", ctypes.c_double),
     ]
 
 
@@ -110,11 +111,14 @@ class Config:
     quant: str = "none"
     out_scale: float = 1.0
     net: str = "tanh"      # "tanh": Q-H-H-Q tanh; "paper": Q-300-300-100-Q LeakyReLU
+    collision: str = "bgk"  # "bgk" or "smagorinsky" (BGK at the local tau_eff)
+    smag_cs: float = 0.0
 
     def _c(self) -> _Cfg:
         return _Cfg(LATTICES[self.lattice], self.nx, self.ny, self.nz, self.batch,
                     self.tau, self.rho0, self.force_kind, self.force_amp, self.force_k,
-                    self.hidden, QUANT[self.quant], self.out_scale, NETS[self.net])
+                    self.hidden, QUANT[self.quant], self.out_scale, NETS[self.net],
+                    COLLISIONS[self.collision], self.smag_cs)
 
     @property
     def Q(self) -> int:

@@ -20,6 +20,8 @@
  *   moments      rho = sum f, rho u = sum f c                   (SI, moments)
  *   equilibrium  2nd-order polynomial f^eq(rho, u)              (eq. feq)
  *   BGK          Omega = -(1/tau)(f - f^eq), dt = 1             (eq. bgk-sm)
+ *                (or with the local tau_eff of the Smagorinsky model, SI,
+ *                "Implementing the Smagorinsky Turbulence Model in LBM")
  *   network      y = MLP(g): tanh net Q-H-H-Q, or the SI's net
  *                Q-300-300-100-Q with LeakyReLU                 (SI, MLP)
  *   update       Omega + (s_out/tau) y                          (eq. nn-model-full)
@@ -80,6 +82,9 @@ typedef struct {
     double out_scale;   /* s_out: the network update is (s_out / tau) y */
     int32_t net;        /* 0: Q-H-H-Q, tanh; 1: the SI's Q-300-300-100-Q, LeakyReLU
                            (hidden must be 300) */
+    int32_t collision;  /* 0: BGK at tau; 1: BGK at the Smagorinsky tau_eff (hidden
+                           must be 0) */
+    double smag_cs;     /* Smagorinsky constant C_s (filter width = 1 lattice unit) */
 } orc_config;
 
 typedef struct {
@@ -299,6 +304,37 @@ static void mlp_forward(const orc_config *cfg, const net_shape *n, const double 
     }
 }
 
+/* Relaxation time of the Smagorinsky model at one node (SI, "Implementing
+ * the Smagorinsky Turbulence Model in LBM"), with dt = 1, c_s^2 = 1/3 and
+ * filter width 1:
+ *   Pi^neq_ab = sum_q c_qa c_qb (f_q - f^eq_q)
+ *   S_ab      = -3 / (2 tau) Pi^neq_ab     (the printed factor 3 tau / 2 is
+ *                                           taken as 3 / (2 tau), see below)
+ *   |S|       = sqrt(2 S_ab S_ab)
+ *   nu_eff    = (tau - 1/2) / 3 + C_s^2 |S|
+ *   tau_eff   = 3 nu_eff + 1/2.
+ * The strain rate follows from the Chapman-Enskog relation
+ * Pi^neq = -2 rho c_s^2 tau S with rho taken as 1, as the SI does; tau is
+ * the molecular relaxation time (explicit, not iterated). */
+static double smagorinsky_tau(const orc_config *cfg, const lattice_t *L, const double g[],
+                              const double geq[]) {
+    double pi[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int q = 0; q < L->Q; ++q) {
+        double d = g[q] - geq[q];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) pi[a][b] += L->c[q][a] * L->c[q][b] * d;
+    }
+    double ss = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double sab = -3.0 / (2.0 * cfg->tau) * pi[a][b];
+            ss += sab * sab;
+        }
+    double smag = sqrt(2.0 * ss);
+    double nu = (cfg->tau - 0.5) / 3.0 + cfg->smag_cs * cfg->smag_cs * smag;
+    return 3.0 * nu + 0.5;
+}
+
 /* Collision of one node: post = g + P(Omega_BGK + (s_out/tau) y) + f^ext. */
 static void collide_node(const orc_config *cfg, const lattice_t *L, const double *theta,
                          node_fwd *s, double post[]) {
@@ -306,7 +342,8 @@ static void collide_node(const orc_config *cfg, const lattice_t *L, const double
     double geq[QMAX], upd[QMAX];
     node_moments(L, s->g, &s->drho, s->j);
     equilibrium_dev(L, cfg->rho0, s->drho, s->j, geq);
-    for (int q = 0; q < Q; ++q) upd[q] = -(s->g[q] - geq[q]) / cfg->tau;
+    double tau = cfg->collision == 1 ? smagorinsky_tau(cfg, L, s->g, geq) : cfg->tau;
+    for (int q = 0; q < Q; ++q) upd[q] = -(s->g[q] - geq[q]) / tau;
     if (cfg->hidden > 0) {
         net_shape n;
         get_net(Q, cfg->hidden, cfg->net, &n);
@@ -335,6 +372,8 @@ static int check_cfg(const orc_config *cfg, lattice_t *L) {
     if (L->D == 2 && cfg->nz != 1) return -1;
     net_shape n;
     if (get_net(L->Q, cfg->hidden, cfg->net, &n)) return -1;
+    if (cfg->collision != 0 && cfg->collision != 1) return -1;
+    if (cfg->collision == 1 && (cfg->hidden != 0 || !(cfg->smag_cs >= 0.0))) return -1;
     return 0;
 }
 
@@ -579,6 +618,7 @@ int orc_step_adjoint(const orc_config *cfg, const double *theta, const double *g
                      const double *lam_n1, double *lam_n, double *dtheta) {
     lattice_t L;
     if (check_cfg(cfg, &L)) return -1;
+    if (cfg->collision != 0) return -3; /* the adjoint covers the fixed-tau collision only */
     int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q, N = nx * ny * nz;
     int64_t P = orc_param_elems(cfg->lattice, cfg->hidden, cfg->net);
     double *scratch_dtheta = NULL;

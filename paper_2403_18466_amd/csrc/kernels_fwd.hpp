@@ -333,6 +333,64 @@ __device__ inline void bgk_update(const float g[L::Q], float rho0, float omega, 
   for (int q = 0; q < L::Q; ++q) upd[q] = (geq[q] - g[q]) * omega;
 }
 
+// sum_q c_qa c_qb d_q with compile-time signs (the first nonzero term starts
+// the sum).
+template <class L, int a, int b, int q = 0>
+__device__ inline float pisum(const float d[L::Q], float acc = 0.f, bool started = false) {
+  if constexpr (q == L::Q) {
+    return started ? acc : 0.f;
+  } else {
+    constexpr int c = comp<L>(q, a) * comp<L>(q, b);
+    if constexpr (c == 0) {
+      return pisum<L, a, b, q + 1>(d, acc, started);
+    } else {
+      const float t = c > 0 ? d[q] : -d[q];
+      return pisum<L, a, b, q + 1>(d, started ? acc + t : t, true);
+    }
+  }
+}
+
+// Relaxation rate 1 / tau_eff of the Smagorinsky model (SI, "Implementing
+// the Smagorinsky Turbulence Model in LBM"; dt = 1, c_s^2 = 1/3, filter
+// width 1):  Pi^neq_ab = sum_q c_qa c_qb (f_q - f^eq_q),
+// |S| = (3 / (2 tau)) sqrt(2 Pi_ab Pi_ab), tau_eff = tau + 3 C_s^2 |S|.
+// c15 = 3 / (2 tau), cs2x3 = 3 C_s^2.
+template <class L>
+__device__ inline float smag_omega(const float g[L::Q], const float geq[L::Q], float tau,
+                                   float c15, float cs2x3) {
+  float d[L::Q];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) d[q] = g[q] - geq[q];
+  const float pxx = pisum<L, 0, 0>(d), pyy = pisum<L, 1, 1>(d), pxy = pisum<L, 0, 1>(d);
+  float diag = pxx * pxx + pyy * pyy, offd = pxy * pxy;
+  if constexpr (L::D == 3) {
+    const float pzz = pisum<L, 2, 2>(d), pxz = pisum<L, 0, 2>(d), pyz = pisum<L, 1, 2>(d);
+    diag = __builtin_fmaf(pzz, pzz, diag);
+    offd = __builtin_fmaf(pxz, pxz, __builtin_fmaf(pyz, pyz, offd));
+  }
+  const float smag = c15 * __builtin_sqrtf(2.f * __builtin_fmaf(2.f, offd, diag));
+  return __builtin_amdgcn_rcpf(__builtin_fmaf(cs2x3, smag, tau));
+}
+
+// BGK part at the Smagorinsky relaxation time.
+template <class L>
+__device__ inline void smag_update(const float g[L::Q], float rho0, float tau, float c15,
+                                   float cs2x3, float upd[L::Q], float& rho, float u[3]) {
+  float drho, j[3];
+  moments<L>(g, drho, j);
+  rho = rho0 + drho;
+  const float inv = __builtin_amdgcn_rcpf(rho);
+  u[0] = j[0] * inv;
+  u[1] = j[1] * inv;
+  u[2] = L::D == 3 ? j[2] * inv : 0.f;
+  const float uu = dot3<L>(u, u);
+  float geq[L::Q];
+  Unroll<L>::feq(drho, rho, u, uu, geq);
+  const float omega = smag_omega<L>(g, geq, tau, c15, cs2x3);
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) upd[q] = (geq[q] - g[q]) * omega;
+}
+
 // Projection of the whole update (kappa layer), then the EDM force, then
 // post = pre + update + force (eq. lbe-sm).
 template <class L>
@@ -360,12 +418,15 @@ __device__ inline void finish_collision(const float g[L::Q], float upd[L::Q], fl
 // of one row (b, z, y); the launch is 1-D over rows x ceil(nx / 256).
 // ---------------------------------------------------------------------------
 // R rows per thread (more loads in flight per thread); NT: non-temporal
-// stores (the next step reads the output from HBM anyway).
-template <class L, int R, bool NT>
+// stores (the next step reads the output from HBM anyway); SMAG: relaxation
+// at the Smagorinsky tau_eff of each node (tau, c15 = 3 / (2 tau),
+// cs2x3 = 3 C_s^2) instead of the fixed rate omega.
+template <class L, int R, bool NT, bool SMAG = false>
 __global__ __launch_bounds__(256) void bgk_step_kernel(const float* __restrict__ Ain,
                                                        float* __restrict__ Aout, Grid G,
                                                        Force Fc, float rho0, float omega,
-                                                       int nxc) {
+                                                       int nxc, float tau = 0.f, float c15 = 0.f,
+                                                       float cs2x3 = 0.f) {
   const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * L::Q) * 4u;
   const rsrc_t src = make_rsrc(Ain, bytes), dst = make_rsrc(Aout, bytes);
   const int nrow_groups = (G.ny + R - 1) / R;
@@ -386,7 +447,10 @@ __global__ __launch_bounds__(256) void bgk_step_kernel(const float* __restrict__
   for (int r = 0; r < R; ++r) {
     if (!t[r].active) continue;
     float upd[L::Q], rho, u[3], F[3];
-    bgk_update<L>(g[r], rho0, omega, upd, rho, u);
+    if constexpr (SMAG)
+      smag_update<L>(g[r], rho0, tau, c15, cs2x3, upd, rho, u);
+    else
+      bgk_update<L>(g[r], rho0, omega, upd, rho, u);
     body_force(Fc, G, t[r].x, t[r].y, t[r].z, F);
     float post[L::Q];
     finish_collision<L>(g[r], upd, rho, u, F, Fc.kind != 0, post);

@@ -165,6 +165,14 @@ lbm_status validate(const lbm_config* c) {
     return fail(LBM_ERR_INVALID, "the three-component sine force needs D3Q19");
   if (c->force_kind != LBM_FORCE_NONE && !std::isfinite(c->force_amp))
     return fail(LBM_ERR_INVALID, "force_amp must be finite");
+  if (c->collision != LBM_COLLISION_BGK && c->collision != LBM_COLLISION_SMAGORINSKY)
+    return fail(LBM_ERR_INVALID, "collision must be LBM_COLLISION_BGK or LBM_COLLISION_SMAGORINSKY");
+  if (c->collision == LBM_COLLISION_SMAGORINSKY) {
+    if (c->hidden != 0)
+      return fail(LBM_ERR_INVALID, "the Smagorinsky collision takes no network (hidden must be 0)");
+    if (!(c->smag_cs >= 0.0) || !std::isfinite(c->smag_cs))
+      return fail(LBM_ERR_INVALID, "smag_cs must be finite and >= 0");
+  }
   if (c->hidden != 0) {
     if (c->net != LBM_NET_TANH && c->net != LBM_NET_LEAKY_300_300_100)
       return fail(LBM_ERR_INVALID, "net must be LBM_NET_TANH or LBM_NET_LEAKY_300_300_100");
@@ -229,14 +237,15 @@ lbm_status run_moments(lbm_ctx* ctx, const float* A, float* rho, float* u, doubl
   return LBM_OK;
 }
 
-template <class L, int R, bool NT>
+template <class L, int R, bool NT, bool SMAG>
 lbm_status launch_bgk_v(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t s) {
   Grid G = grid_of(ctx->cfg);
+  const lbm_config& c = ctx->cfg;
   int nxc = (G.nx + 255) / 256;
   long long nblk = (long long)nxc * ((G.ny + R - 1) / R) * G.nz * G.batch;
-  hipLaunchKernelGGL((bgk_step_kernel<L, R, NT>), dim3((unsigned)nblk), dim3(256), 0, s, Ain,
-                     Aout, G, force_of(ctx->cfg), (float)ctx->cfg.rho0,
-                     (float)(1.0 / ctx->cfg.tau), nxc);
+  hipLaunchKernelGGL((bgk_step_kernel<L, R, NT, SMAG>), dim3((unsigned)nblk), dim3(256), 0, s,
+                     Ain, Aout, G, force_of(c), (float)c.rho0, (float)(1.0 / c.tau), nxc,
+                     (float)c.tau, (float)(1.5 / c.tau), (float)(3.0 * c.smag_cs * c.smag_cs));
   LBM_LAUNCHED("bgk_step_kernel");
   return LBM_OK;
 }
@@ -245,7 +254,9 @@ template <class L>
 lbm_status launch_bgk(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t s) {
   // one node per thread with non-temporal stores measured fastest (more rows
   // per thread lowered the achieved bandwidth)
-  return launch_bgk_v<L, 1, true>(ctx, Ain, Aout, s);
+  if (ctx->cfg.collision == LBM_COLLISION_SMAGORINSKY)
+    return launch_bgk_v<L, 1, true, true>(ctx, Ain, Aout, s);
+  return launch_bgk_v<L, 1, true, false>(ctx, Ain, Aout, s);
 }
 
 // Workgroups for a persistent kernel: as many as fit on the chip at once,
@@ -605,6 +616,8 @@ lbm_status lbm_step_backward(lbm_ctx* ctx, const float* A_n, const float* theta,
     return fail(LBM_ERR_INVALID, "lam_n must not alias lam_n1 or A_n");
   if (ctx->cfg.hidden != 0 && ctx->cfg.net != LBM_NET_TANH)
     return fail(LBM_ERR_UNSUPPORTED, "the adjoint of LBM_NET_LEAKY_300_300_100 is not implemented");
+  if (ctx->cfg.collision != LBM_COLLISION_BGK)
+    return fail(LBM_ERR_UNSUPPORTED, "the adjoint of the Smagorinsky collision is not implemented");
   if (ctx->cfg.hidden != 0) {
     if (!theta || !dtheta) return fail(LBM_ERR_INVALID, "theta and dtheta must be given");
     if (!ws) return fail(LBM_ERR_INVALID, "workspace is null");

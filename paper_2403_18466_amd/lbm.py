@@ -22,10 +22,12 @@ LBM_D2Q9, LBM_D3Q19 = 0, 1
 LBM_MLP_FP32, LBM_MLP_BF16, LBM_MLP_FP16 = 1, 2, 3
 LBM_FORCE_NONE, LBM_FORCE_KOLMOGOROV, LBM_FORCE_SINE3 = 0, 1, 2
 LBM_NET_TANH, LBM_NET_LEAKY_300_300_100 = 0, 1
+LBM_COLLISION_BGK, LBM_COLLISION_SMAGORINSKY = 0, 1
 
 LATTICES = {"D2Q9": LBM_D2Q9, "D3Q19": LBM_D3Q19}
 PRECISIONS = {"fp32": LBM_MLP_FP32, "bf16": LBM_MLP_BF16, "fp16": LBM_MLP_FP16}
 NETS = {"tanh": LBM_NET_TANH, "paper": LBM_NET_LEAKY_300_300_100}
+COLLISIONS = {"bgk": LBM_COLLISION_BGK, "smagorinsky": LBM_COLLISION_SMAGORINSKY}
 
 # Every symbol include/lbm.h declares.
 EXPORTS = (
@@ -45,6 +47,7 @@ class lbm_config(ctypes.Structure):
         ("force_amp", ctypes.c_double),
         ("hidden", ctypes.c_int32), ("mlp_prec", ctypes.c_int32),
         ("out_scale", ctypes.c_double), ("net", ctypes.c_int32),
+        ("collision", ctypes.c_int32), ("smag_cs", ctypes.c_double),
     ]
 
 
@@ -142,6 +145,8 @@ class Config:
     mlp_prec: str = "fp32"
     out_scale: float = 1.0
     net: str = "tanh"   # "tanh": Q-H-H-Q; "paper": Q-300-300-100-Q LeakyReLU (hidden=300)
+    collision: str = "bgk"  # "bgk" or "smagorinsky" (hidden must be 0)
+    smag_cs: float = 0.0
 
     @property
     def Q(self):
@@ -159,7 +164,8 @@ class Config:
         return lbm_config(LATTICES[self.lattice], self.nx, self.ny, self.nz, self.batch,
                           float(self.tau), float(self.rho0), int(self.force_kind),
                           int(self.force_k), float(self.force_amp), int(self.hidden),
-                          PRECISIONS[self.mlp_prec], float(self.out_scale), NETS[self.net])
+                          PRECISIONS[self.mlp_prec], float(self.out_scale), NETS[self.net],
+                          COLLISIONS[self.collision], float(self.smag_cs))
 
 
 # ----------------------------------------------------------------- C names

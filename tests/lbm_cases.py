@@ -45,7 +45,8 @@ def lib_config(ocfg, prec="fp32"):
                       batch=ocfg.batch, tau=ocfg.tau, rho0=ocfg.rho0,
                       force_kind=ocfg.force_kind, force_k=ocfg.force_k,
                       force_amp=ocfg.force_amp, hidden=ocfg.hidden, mlp_prec=prec,
-                      out_scale=ocfg.out_scale, net=ocfg.net)
+                      out_scale=ocfg.out_scale, net=ocfg.net, collision=ocfg.collision,
+                      smag_cs=ocfg.smag_cs)
 
 
 def fourier_state(ocfg, umax=0.05, seed=0, kmax=4):
