@@ -253,6 +253,34 @@ lbm_status lbm_box_filter(const float* src, float* dst, int32_t batch, int32_t c
                           int32_t nx, int32_t ny, int32_t nz, int32_t factor,
                           hipStream_t stream);
 
+/* Sub-sampling filter of the SI's training set ("Definition of the Training
+ * Dataset": one lattice point in every `factor` along each axis) for
+ * pull-shifted population arrays: the coarse canonical population at node X
+ * is the fine one at factor * X, which in the pull-shifted form of both
+ * grids reads
+ *   dst_q(X) = src_q(factor X + (factor - 1) c_q)   (periodic).
+ * src: [batch][Q][nz][ny][nx] of `lattice`; dst: [batch][Q][nz/f][ny/f][nx/f]
+ * (nz is not divided for D2Q9, where nz == 1).  Sizes must be multiples of
+ * factor.  src != dst. */
+lbm_status lbm_subsample(int32_t lattice, const float* src, float* dst, int32_t batch,
+                         int32_t nx, int32_t ny, int32_t nz, int32_t factor, hipStream_t stream);
+
+/* Population loss of eq. nn-loss on a node subset S:
+ *   L = sum over x in S and q of (A_q(x) - T_q(x))^2,
+ * A the model's state after the unrolled steps, T the target, both
+ * population arrays of the context.  Because they are pull-shifted,
+ * A_q(x) is the post-collision population of node x of the last step: the
+ * comparison of post-collision values of the SI needs no separate
+ * anti-streaming.  nodes: device int32[n_nodes] of flat indices
+ * b * (nx ny nz) + (z ny + y) nx + x, which must be distinct; an index out of
+ * range makes *loss NaN.  loss: device float64[1].  dLdA (may be null):
+ * written with 2 (A - T) at the listed nodes and left untouched elsewhere
+ * (zero it first to obtain the full gradient).  Summed in float64 in a
+ * fixed order. */
+lbm_status lbm_loss_population_sse(lbm_ctx* ctx, const float* A, const float* target,
+                                   const int32_t* nodes, int32_t n_nodes, double* loss,
+                                   float* dLdA, hipStream_t stream);
+
 const char* lbm_status_str(lbm_status s);
 const char* lbm_last_error(void);
 

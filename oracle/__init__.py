@@ -77,6 +77,9 @@ def _load():
             ("orc_moments", [cp, dp, dp, dp, dp]),
             ("orc_step_adjoint", [cp, dp, dp, dp, dp, dp]),
             ("orc_loss_velocity_mse", [cp, dp, dp, dp, dp]),
+            ("orc_subsample", [cp, dp, ctypes.c_int, dp]),
+            ("orc_loss_population_sse", [cp, dp, dp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
+                                         dp, dp]),
         ]:
             f = getattr(_lib, name)
             f.argtypes = args
@@ -240,6 +243,33 @@ def loss_velocity_mse(cfg: Config, g, u_target, want_grad: bool = True):
     return loss.value, grad
 
 
+def subsample(cfg: Config, g, factor: int):
+    """Sub-sampling filter of the SI's training set on a canonical state of
+    the fine configuration cfg."""
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    assert g.shape == cfg.state_shape
+    fz = factor if cfg.D == 3 else 1
+    out = np.empty((cfg.batch, cfg.Q, cfg.nz // fz, cfg.ny // factor, cfg.nx // factor))
+    c = cfg._c()
+    _check(_load().orc_subsample(ctypes.byref(c), _ptr(g), factor, _ptr(out)), "subsample")
+    return out
+
+
+def loss_population_sse(cfg: Config, g_model, g_target, nodes, want_grad: bool = True):
+    """eq. nn-loss on the node subset `nodes` (flat indices) for canonical
+    pre-collision states; returns (loss, dL/dg_model or None)."""
+    gm = np.ascontiguousarray(g_model, dtype=np.float64)
+    gt = np.ascontiguousarray(g_target, dtype=np.float64)
+    nd = np.ascontiguousarray(nodes, dtype=np.int32)
+    loss = ctypes.c_double()
+    grad = np.empty_like(gm) if want_grad else None
+    c = cfg._c()
+    _check(_load().orc_loss_population_sse(
+        ctypes.byref(c), _ptr(gm), _ptr(gt), nd.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        int(nd.size), ctypes.byref(loss), _ptr(grad)), "loss_population_sse")
+    return loss.value, grad
+
+
 def round_bf16(v: float) -> float:
     return _load().orc_round_bf16(float(v))
 
@@ -248,8 +278,11 @@ def round_fp16(v: float) -> float:
     return _load().orc_round_fp16(float(v))
 
 
-def unrolled_loss_and_grad(cfg: Config, g0, theta, u_target, nsteps: int, ckpt: int = 0):
+def unrolled_loss_and_grad(cfg: Config, g0, theta, u_target, nsteps: int, ckpt: int = 0,
+                           loss_fn=None):
     """Loss after `nsteps` steps from g0 and its gradient w.r.t. theta and g0.
+    The loss is the velocity MSE against u_target, or loss_fn(g) -> (loss,
+    dL/dg) when given.
 
     Reverse-mode through the whole trajectory (the unrolled training of the
     SI, "Unrolled training").  With ckpt > 0 only every ckpt-th state is kept
@@ -262,7 +295,7 @@ def unrolled_loss_and_grad(cfg: Config, g0, theta, u_target, nsteps: int, ckpt: 
         if ckpt <= 0 or n % ckpt == 0:
             states[n] = g
         g = step(cfg, g, theta)
-    loss, lam = loss_velocity_mse(cfg, g, u_target)
+    loss, lam = loss_velocity_mse(cfg, g, u_target) if loss_fn is None else loss_fn(g)
     dtheta = np.zeros(cfg.n_params, np.float64)
     n = nsteps
     while n > 0:

@@ -694,3 +694,60 @@ int orc_loss_velocity_mse(const orc_config *cfg, const double *g, const double *
     *loss = acc / count;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Training set of the SI ("Definition of the Training Dataset")             */
+/* ------------------------------------------------------------------------ */
+
+/* Sub-sampling filter: the coarse grid keeps one lattice point in every
+ * `factor` along each axis (only along x and y for 2-D lattices).  cfg is
+ * the fine configuration; g is canonical, g_coarse [B][Q][nz/f][ny/f][nx/f]. */
+int orc_subsample(const orc_config *cfg, const double *g, int factor, double *g_coarse) {
+    lattice_t L;
+    if (check_cfg(cfg, &L) || factor < 1) return -1;
+    int fz = L.D == 3 ? factor : 1;
+    if (cfg->nx % factor || cfg->ny % factor || cfg->nz % fz) return -1;
+    int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q;
+    int64_t cx = nx / factor, cy = ny / factor, cz = nz / fz;
+    for (int64_t b = 0; b < cfg->batch; ++b)
+        for (int64_t q = 0; q < Q; ++q)
+            for (int64_t z = 0; z < cz; ++z)
+                for (int64_t y = 0; y < cy; ++y)
+                    for (int64_t x = 0; x < cx; ++x)
+                        g_coarse[(((b * Q + q) * cz + z) * cy + y) * cx + x] =
+                            g[(((b * Q + q) * nz + z * fz) * ny + y * factor) * nx + x * factor];
+    return 0;
+}
+
+/* Population loss of eq. nn-loss on a node subset S.  g_model and g_target
+ * are canonical pre-collision states at the end of the trajectory; the
+ * post-collision populations they come from are recovered by the inverse of
+ * the streaming (reversed directions, SI Fig. 2):
+ *   post_q(x) = g_q(x + c_q).
+ * L = sum over x in S and q of (post_model_q(x) - post_target_q(x))^2.
+ * nodes: flat indices b * N + (z ny + y) nx + x.  dLdg (may be NULL) is the
+ * gradient with respect to g_model, zero outside the nodes' sources. */
+int orc_loss_population_sse(const orc_config *cfg, const double *g_model, const double *g_target,
+                            const int32_t *nodes, int n_nodes, double *loss, double *dLdg) {
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q, N = nx * ny * nz;
+    if (dLdg) memset(dLdg, 0, sizeof(double) * (size_t)(cfg->batch * Q * N));
+    double acc = 0.0;
+    for (int i = 0; i < n_nodes; ++i) {
+        int64_t k = nodes[i];
+        if (k < 0 || k >= cfg->batch * N) return -1;
+        int64_t b = k / N, n = k % N;
+        int64_t x = n % nx, y = (n / nx) % ny, z = n / (nx * ny);
+        for (int q = 0; q < Q; ++q) {
+            int64_t xs = wrap(x + L.c[q][0], nx), ys = wrap(y + L.c[q][1], ny);
+            int64_t zs = wrap(z + L.c[q][2], nz);
+            int64_t e = (b * Q + q) * N + (zs * ny + ys) * nx + xs;
+            double d = g_model[e] - g_target[e];
+            acc += d * d;
+            if (dLdg) dLdg[e] += 2.0 * d;
+        }
+    }
+    *loss = acc;
+    return 0;
+}

@@ -124,4 +124,78 @@ __global__ __launch_bounds__(256) void box_filter_kernel(const float* __restrict
   dst[n] = acc / (float)(f * f * fz);
 }
 
+// Sub-sampling filter of the SI's training set ("Definition of the Training
+// Dataset": keep one lattice point in every f along each axis) applied to a
+// pull-shifted fine state: the coarse canonical population at X is the fine
+// one at f X, and in the pull-shifted form of both grids that reads
+//   dst_q(X) = src_q(f X + (f - 1) c_q)   (periodic on the fine grid).
+// fz = f for 3-D grids, 1 for 2-D ones.
+template <class L>
+__global__ __launch_bounds__(256) void subsample_kernel(const float* __restrict__ src,
+                                                        float* __restrict__ dst, int batch,
+                                                        int nx, int ny, int nz, int f, int fz) {
+  const int cx = nx / f, cy = ny / f, cz = nz / fz;
+  const long long total = (long long)batch * cz * cy * cx;
+  const long long n = blockIdx.x * 256LL + threadIdx.x;
+  if (n >= total) return;
+  const int X = (int)(n % cx);
+  long long r = n / cx;
+  const int Y = (int)(r % cy);
+  r /= cy;
+  const int Z = (int)(r % cz);
+  const int b = (int)(r / cz);
+  const long long fplane = (long long)nx * ny * nz, cplane = (long long)cx * cy * cz;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    int xs = (X * f + (f - 1) * L::cx[q]) % nx, ys = (Y * f + (f - 1) * L::cy[q]) % ny,
+        zs = (Z * fz + (fz - 1) * L::cz[q]) % nz;
+    xs += xs < 0 ? nx : 0;
+    ys += ys < 0 ? ny : 0;
+    zs += zs < 0 ? nz : 0;
+    dst[((long long)b * L::Q + q) * cplane + ((long long)Z * cy + Y) * cx + X] =
+        src[((long long)b * L::Q + q) * fplane + ((long long)zs * ny + ys) * nx + xs];
+  }
+}
+
+// Population loss of eq. nn-loss on a node subset S: L = sum over the listed
+// nodes and q of (A_q(x) - T_q(x))^2, with A the model's state after the
+// unrolled steps and T the target, both pull-shifted, so that A_q(x) is the
+// post-collision population of node x (the anti-streaming of the SI's
+// Fig. 2 is the layout itself).  nodes: flat indices b * plane + node,
+// distinct.  dLdA (may be null) gets 2 (A - T) at the listed nodes only.  An
+// index outside [0, batch * plane) makes the loss NaN.  Block partials in
+// float64, reduced in a fixed order.
+template <class L>
+__global__ __launch_bounds__(256) void population_sse_kernel(const float* __restrict__ A,
+                                                             const float* __restrict__ T,
+                                                             const int* __restrict__ nodes,
+                                                             int n, float* __restrict__ dLdA,
+                                                             double* __restrict__ partial, Grid G) {
+  double acc = 0.0;
+  const long long total = (long long)G.plane * G.batch;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const int k = nodes[i];
+    if (k < 0 || k >= total) {
+      acc += __builtin_nan("");
+      continue;
+    }
+    const long long b = k / G.plane, node = k - b * G.plane;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const long long e = (b * L::Q + q) * G.plane + node;
+      const double d = (double)A[e] - (double)T[e];
+      acc += d * d;
+      if (dLdA) dLdA[e] = (float)(2.0 * d);
+    }
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 }  // namespace lbm

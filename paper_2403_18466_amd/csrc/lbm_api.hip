@@ -680,6 +680,58 @@ lbm_status lbm_box_filter(const float* src, float* dst, int32_t batch, int32_t c
   LBM_GUARD_END
 }
 
+lbm_status lbm_subsample(int32_t lattice, const float* src, float* dst, int32_t batch,
+                         int32_t nx, int32_t ny, int32_t nz, int32_t factor, hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  if (!src || !dst) return fail(LBM_ERR_INVALID, "null array");
+  if (src == dst) return fail(LBM_ERR_INVALID, "src and dst must differ");
+  if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) return fail(LBM_ERR_INVALID, "unknown lattice");
+  if (batch < 1 || nx < 1 || ny < 1 || nz < 1 || factor < 1)
+    return fail(LBM_ERR_INVALID, "sizes must be >= 1");
+  if (lattice == LBM_D2Q9 && nz != 1) return fail(LBM_ERR_INVALID, "D2Q9 needs nz == 1");
+  const int fz = nz > 1 ? factor : 1;
+  if (nx % factor || ny % factor || nz % fz)
+    return fail(LBM_ERR_INVALID, "grid sizes must be multiples of factor");
+  if ((double)batch * lattice_q(lattice) * nx * (double)ny * nz >= 1073741824.0)
+    return fail(LBM_ERR_INVALID, "batch*Q*nx*ny*nz must stay below 2^30 elements");
+  const long long total = (long long)batch * (nz / fz) * (ny / factor) * (nx / factor);
+  if (lattice == LBM_D2Q9)
+    hipLaunchKernelGGL(subsample_kernel<D2Q9>, dim3(blocks_for(total)), dim3(256), 0, stream, src,
+                       dst, batch, nx, ny, nz, factor, fz);
+  else
+    hipLaunchKernelGGL(subsample_kernel<D3Q19>, dim3(blocks_for(total)), dim3(256), 0, stream, src,
+                       dst, batch, nx, ny, nz, factor, fz);
+  LBM_LAUNCHED("subsample_kernel");
+  return LBM_OK;
+  LBM_GUARD_END
+}
+
+lbm_status lbm_loss_population_sse(lbm_ctx* ctx, const float* A, const float* target,
+                                   const int32_t* nodes, int32_t n_nodes, double* loss,
+                                   float* dLdA, hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  lbm_status st = check_ctx(ctx);
+  if (st != LBM_OK) return st;
+  if (!A || !target || !nodes || !loss) return fail(LBM_ERR_INVALID, "null array");
+  if (n_nodes < 1) return fail(LBM_ERR_INVALID, "n_nodes must be >= 1");
+  if (dLdA == A || dLdA == target) return fail(LBM_ERR_INVALID, "dLdA must not alias A or target");
+  Grid G = grid_of(ctx->cfg);
+  int nblk = (int)blocks_for(n_nodes);
+  if (nblk > MOM_BLOCKS) nblk = MOM_BLOCKS;
+  if (ctx->cfg.lattice == LBM_D2Q9)
+    hipLaunchKernelGGL(population_sse_kernel<D2Q9>, dim3(nblk), dim3(256), 0, stream, A, target,
+                       nodes, n_nodes, dLdA, ctx->partial, G);
+  else
+    hipLaunchKernelGGL(population_sse_kernel<D3Q19>, dim3(nblk), dim3(256), 0, stream, A, target,
+                       nodes, n_nodes, dLdA, ctx->partial, G);
+  LBM_LAUNCHED("population_sse_kernel");
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, stream, ctx->partial, nblk, 1.0,
+                     loss);
+  LBM_LAUNCHED("sum_partials_kernel");
+  return LBM_OK;
+  LBM_GUARD_END
+}
+
 const char* lbm_status_str(lbm_status s) {
   switch (s) {
     case LBM_OK: return "LBM_OK";

@@ -34,7 +34,7 @@ EXPORTS = (
     "lbm_create", "lbm_destroy", "lbm_state_elems", "lbm_param_elems", "lbm_workspace_bytes",
     "lbm_lattice_tables", "lbm_init", "lbm_step", "lbm_moments", "lbm_shift",
     "lbm_step_backward", "lbm_loss_velocity_mse", "lbm_adam", "lbm_box_filter",
-    "lbm_status_str", "lbm_last_error",
+    "lbm_subsample", "lbm_loss_population_sse", "lbm_status_str", "lbm_last_error",
 )
 
 
@@ -85,6 +85,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_loss_velocity_mse": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "lbm_adam": ([vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, dbl, i32, vp], ctypes.c_int),
         "lbm_box_filter": ([vp, vp, i32, i32, i32, i32, i32, i32, vp], ctypes.c_int),
+        "lbm_subsample": ([i32, vp, vp, i32, i32, i32, i32, i32, vp], ctypes.c_int),
+        "lbm_loss_population_sse": ([vp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
         "lbm_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "lbm_last_error": ([], ctypes.c_char_p),
     }
@@ -286,6 +288,27 @@ def lbm_box_filter(src, dst, batch, channels, nx, ny, nz, factor, stream=None):
         batch, channels, nx, ny, nz, factor, _stream(stream)), "lbm_box_filter")
 
 
+def lbm_subsample(lattice: str, src, dst, batch, nx, ny, nz, factor, stream=None):
+    q = 9 if lattice == "D2Q9" else 19
+    fz = factor if nz > 1 else 1
+    _check(load_library().lbm_subsample(
+        LATTICES[lattice], _ptr(src, torch.float32, batch * q * nx * ny * nz, "src"),
+        _ptr(dst, torch.float32, batch * q * (nx // factor) * (ny // factor) * (nz // fz), "dst"),
+        batch, nx, ny, nz, factor, _stream(stream)), "lbm_subsample")
+
+
+def lbm_loss_population_sse(ctx, cfg: Config, A, target, nodes, loss, dLdA=None, stream=None):
+    n = lbm_state_elems(ctx)
+    if nodes.dtype != torch.int32 or nodes.device.type != "cuda" or not nodes.is_contiguous():
+        raise ValueError("nodes must be a contiguous int32 device tensor")
+    _check(load_library().lbm_loss_population_sse(
+        ctx, _ptr(A, torch.float32, n, "A"), _ptr(target, torch.float32, n, "target"),
+        ctypes.c_void_p(nodes.data_ptr()), int(nodes.numel()),
+        _ptr(loss, torch.float64, 1, "loss"),
+        _ptr(dLdA, torch.float32, n, "dLdA", allow_none=True), _stream(stream)),
+        "lbm_loss_population_sse")
+
+
 # ------------------------------------------------------------ convenience
 class Lattice:
     """A context plus the configuration, with tensor-allocating helpers."""
@@ -352,6 +375,14 @@ class Lattice:
         lbm_step_backward(self.ctx, self.cfg, A_n, theta, lam_n1, lam_n, dtheta,
                           self.workspace() if self.cfg.hidden else None)
         return lam_n, dtheta
+
+    def loss_population_sse(self, A, target, nodes, want_grad=True):
+        """eq. nn-loss on the node subset `nodes` (distinct flat indices);
+        the gradient is zero outside the subset."""
+        loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        g = torch.zeros_like(A) if want_grad else None
+        lbm_loss_population_sse(self.ctx, self.cfg, A, target, nodes, loss, g)
+        return loss, g
 
     def loss_velocity_mse(self, A, u_target, want_grad=True):
         loss = torch.empty(1, dtype=torch.float64, device=self.device)

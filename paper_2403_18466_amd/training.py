@@ -35,13 +35,15 @@ class NLBMStep(torch.autograd.Function):
 
 
 def unrolled_loss_and_grad(L: "lbm.Lattice", A0, theta, u_target, nsteps: int, ckpt: int = 8,
-                           want_dA0: bool = False):
-    """Velocity-MSE loss after `nsteps` steps from A0 and its gradient.
+                           want_dA0: bool = False, loss_fn=None):
+    """Loss after `nsteps` steps from A0 and its gradient.
 
-    Forward keeps the state at every multiple of `ckpt` (plus A0); the
-    backward pass walks the segments in reverse, recomputes each segment's
-    states from its checkpoint, and applies lbm_step_backward step by step.
-    Memory: nsteps/ckpt checkpoints + ckpt segment states + 2 adjoint buffers.
+    The loss is the velocity MSE against u_target, or loss_fn(A) -> (loss,
+    dL/dA) when given (e.g. the population loss on a node subset).  Forward
+    keeps the state at every multiple of `ckpt` (plus A0); the backward pass
+    walks the segments in reverse, recomputes each segment's states from its
+    checkpoint, and applies lbm_step_backward step by step.  Memory:
+    nsteps/ckpt checkpoints + ckpt segment states + 2 adjoint buffers.
     Returns (loss [1] float64 device tensor, dtheta, dA0 or None)."""
     assert nsteps >= 1 and ckpt >= 1
     ckpts = {0: A0}
@@ -52,7 +54,10 @@ def unrolled_loss_and_grad(L: "lbm.Lattice", A0, theta, u_target, nsteps: int, c
         a, b = res, (a if res is b else b)
         if (n + 1) % ckpt == 0 and n + 1 < nsteps:
             ckpts[n + 1] = a.clone()
-    loss, lam = L.loss_velocity_mse(a, u_target, want_grad=True)
+    if loss_fn is None:
+        loss, lam = L.loss_velocity_mse(a, u_target, want_grad=True)
+    else:
+        loss, lam = loss_fn(a)
     dtheta = torch.zeros(L.n_param, dtype=torch.float32, device=L.device)
     lam_next = torch.empty_like(lam)
     ws = L.workspace()
