@@ -146,7 +146,9 @@ typedef struct {
  * ordered (one stream, or synchronised streams).  With
  * LBM_NET_LEAKY_300_300_100 it also holds the weights in the kernel's
  * fragment order (about 0.3 MB in bf16/fp16, 0.6 MB in fp32, refreshed from
- * theta by every lbm_step call) and its index table (0.6 MB).  Limit:
+ * theta by every lbm_step call) and its index table (0.6 MB), plus the
+ * adjoint's padded W and W^T (0.6 MB in bf16/fp16, 1.1 MB in fp32) and its
+ * index table (1.1 MB).  Limit:
  * batch * Q * nx * ny * nz < 2^30 elements (each population array below
  * 4 GiB, the range of the kernels' 32-bit byte offsets).  Returns
  * LBM_ERR_INVALID or LBM_ERR_UNSUPPORTED with the reason in
@@ -219,8 +221,12 @@ lbm_status lbm_shift(lbm_ctx* ctx, const float* src, float* dst, int32_t directi
  * precision.  ws: device workspace of at least lbm_workspace_bytes() bytes
  * for the per-workgroup partial parameter gradients, which are summed in a
  * fixed order (the result is bit-reproducible).  dtheta may be null only
- * when hidden == 0.  lam_n must not alias lam_n1 or A_n.  Not implemented
- * for LBM_NET_LEAKY_300_300_100 (LBM_ERR_UNSUPPORTED). */
+ * when hidden == 0.  lam_n must not alias lam_n1 or A_n.
+ * With LBM_NET_LEAKY_300_300_100 the adjoint runs as dense products over the
+ * node dimension and keeps every hidden activation in the workspace (about
+ * 6 KB per node in bf16/fp16, 12 KB in fp32: meant for training grids such
+ * as 32^3 - 64^3); the weights are repacked from theta by the call.  Not
+ * implemented for LBM_COLLISION_SMAGORINSKY (LBM_ERR_UNSUPPORTED). */
 lbm_status lbm_step_backward(lbm_ctx* ctx, const float* A_n, const float* theta,
                              const float* lam_n1, float* lam_n, float* dtheta, void* ws,
                              size_t ws_bytes, hipStream_t stream);

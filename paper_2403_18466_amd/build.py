@@ -22,6 +22,7 @@ SOURCES = [
     # canonicalisation; the wide step has no NaN tests)
     (os.path.join(CSRC, "wide.hip"), ("-mllvm", "-amdgpu-sched-strategy=max-ilp",
                                       "-mno-amdgpu-ieee", "-fno-honor-nans")),
+    (os.path.join(CSRC, "wide_bwd.hip"), ()),
 ]
 
 

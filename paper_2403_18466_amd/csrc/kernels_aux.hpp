@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ A,
 }
 
 // out = scale * sum of n partials, one block, fixed order.
-__global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ partial,
+static __global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ partial,
                                                            int n, double scale,
                                                            double* __restrict__ out) {
   __shared__ double red[256];
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restr
 }
 
 // Adam with L2 weight decay folded into the gradient.
-__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p,
+static __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p,
                                                    const float* __restrict__ grad,
                                                    float* __restrict__ m, float* __restrict__ v,
                                                    long long n, float lr, float b1, float b2,
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p,
 }
 
 // dst[b][c][Z][Y][X] = mean over the f x f (x f) block of src.
-__global__ __launch_bounds__(256) void box_filter_kernel(const float* __restrict__ src,
+static __global__ __launch_bounds__(256) void box_filter_kernel(const float* __restrict__ src,
                                                          float* __restrict__ dst, int batch,
                                                          int ch, int nx, int ny, int nz, int f,
                                                          int fz) {

@@ -458,7 +458,7 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
 // Block = 64 parameters x 4 slices; slice s sums b = s, s + 4, ... with two
 // independent accumulators; the four slice sums are combined in slice order.
 // The order is fixed, so the result is bit-reproducible.
-__global__ __launch_bounds__(256) void grad_reduce_kernel(const float* __restrict__ part, int nb,
+static __global__ __launch_bounds__(256) void grad_reduce_kernel(const float* __restrict__ part, int nb,
                                                           int np, float* __restrict__ dtheta) {
   const int pl = threadIdx.x & 63, sl = threadIdx.x >> 6;
   const int p = blockIdx.x * 64 + pl;

@@ -15,6 +15,7 @@
 #include "kernels_fwd.hpp"
 #include "lbm.h"
 #include "wide.hpp"
+#include "wide_bwd.hpp"
 
 #include <vector>
 
@@ -30,6 +31,9 @@ struct lbm_ctx {
   int* wide_idx;
   unsigned char* wide_packed;
   int wide_nw, wide_nb;
+  // its adjoint: gather table and packed padded W, W^T and bias vectors
+  int* wide_bidx;
+  unsigned char* wide_bpacked;
 };
 
 namespace {
@@ -132,6 +136,43 @@ std::vector<int> wide_index() {
   for (int i = 0; i < 16 * WL::T2; ++i) b[WL::fb2 + i] = i < WL::N2 ? WL::ob2 + i : -1;
   for (int i = 0; i < 16 * WL::T3; ++i) b[WL::fb3 + i] = i < WL::N3 ? WL::ob3 + i : -1;
   for (int i = 0; i < 16 * WL::T4; ++i) b[WL::fb4 + i] = i < Q ? WL::ob4 + i : -1;
+  return idx;
+}
+
+// Gather table of the adjoint's padded matrices (see WideBwd): -1 is 0, -2
+// is the constant 1 of the padded bias columns.
+template <int Q>
+std::vector<int> wide_bwd_index() {
+  using W = WideBwd<Q>;
+  std::vector<int> idx((size_t)W::nw + W::nb, -1);
+  for (int o = 0; o < W::D1; ++o)
+    for (int k = 0; k < W::D0; ++k) {
+      const int v = o < W::N1 ? (k < Q ? W::pW1 + o * Q + k : (k == Q ? W::pb1 + o : -1)) : -1;
+      idx[W::oW1 + o * W::D0 + k] = v;
+      idx[W::oT1 + k * W::D1 + o] = v;
+    }
+  for (int o = 0; o < W::D2; ++o)
+    for (int k = 0; k < W::D1; ++k) {
+      const int v = o < W::N2 && k < W::N1 ? W::pW2 + o * W::N1 + k : -1;
+      idx[W::oW2 + o * W::D1 + k] = v;
+      idx[W::oT2 + k * W::D2 + o] = v;
+    }
+  for (int o = 0; o < W::D3; ++o)
+    for (int k = 0; k < W::D2; ++k) {
+      const int v = o < W::N3 && k < W::N2 ? W::pW3 + o * W::N2 + k : -1;
+      idx[W::oW3 + o * W::D2 + k] = v;
+      idx[W::oT3 + k * W::D3 + o] = v;
+    }
+  for (int o = 0; o < W::D4; ++o)
+    for (int k = 0; k < W::D3; ++k) {
+      const int v = o < Q && k < W::N3 ? W::pW4 + o * W::N3 + k : -1;
+      idx[W::oW4 + o * W::D3 + k] = v;
+      idx[W::oT4 + k * W::D4 + o] = v;
+    }
+  int* v = idx.data() + W::nw;
+  for (int j = 0; j < W::D1; ++j) v[W::fE1 + j] = j == W::ONE1 ? -2 : -1;
+  for (int j = 0; j < W::D2; ++j) v[W::fB2 + j] = j < W::N2 ? W::pb2 + j : (j == W::ONE1 ? -2 : -1);
+  for (int j = 0; j < W::D3; ++j) v[W::fB3 + j] = j < W::N3 ? W::pb3 + j : (j == W::ONE3 ? -2 : -1);
   return idx;
 }
 
@@ -457,6 +498,8 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   ctx->wide_idx = nullptr;
   ctx->wide_packed = nullptr;
   ctx->wide_nw = ctx->wide_nb = 0;
+  ctx->wide_bidx = nullptr;
+  ctx->wide_bpacked = nullptr;
   size_t bytes = sizeof(double) * 3 * MOM_BLOCKS * (size_t)cfg->batch;
   hipError_t e = hipMalloc(&ctx->partial, bytes);
   if (e != hipSuccess) {
@@ -480,6 +523,12 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     if (e == hipSuccess) e = hipMalloc(&ctx->wide_packed, (size_t)pbytes);
     if (e == hipSuccess)
       e = hipMemcpy(ctx->wide_idx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice);
+    std::vector<int> bidx = cfg->lattice == LBM_D2Q9 ? wide_bwd_index<9>() : wide_bwd_index<19>();
+    const size_t bbytes = (size_t)WideBwd<9>::nw * eb + 4 * (size_t)WideBwd<9>::nb;
+    if (e == hipSuccess) e = hipMalloc(&ctx->wide_bidx, sizeof(int) * bidx.size());
+    if (e == hipSuccess) e = hipMalloc(&ctx->wide_bpacked, bbytes);
+    if (e == hipSuccess)
+      e = hipMemcpy(ctx->wide_bidx, bidx.data(), sizeof(int) * bidx.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       lbm_destroy(ctx);
       return fail(LBM_ERR_HIP, std::string("allocation of the wide-network buffers: ") +
@@ -497,6 +546,8 @@ lbm_status lbm_destroy(lbm_ctx* ctx) {
   if (ctx->partial) (void)hipFree(ctx->partial);
   if (ctx->wide_idx) (void)hipFree(ctx->wide_idx);
   if (ctx->wide_packed) (void)hipFree(ctx->wide_packed);
+  if (ctx->wide_bidx) (void)hipFree(ctx->wide_bidx);
+  if (ctx->wide_bpacked) (void)hipFree(ctx->wide_bpacked);
   delete ctx;
   return LBM_OK;
   LBM_GUARD_END
@@ -514,7 +565,12 @@ size_t lbm_param_elems(const lbm_ctx* ctx) {
 }
 
 size_t lbm_workspace_bytes(const lbm_ctx* ctx) {
-  if (!ctx || ctx->cfg.hidden == 0 || ctx->cfg.net != LBM_NET_TANH) return 0;
+  if (!ctx || ctx->cfg.hidden == 0) return 0;
+  if (ctx->cfg.net == LBM_NET_LEAKY_300_300_100) {
+    const lbm_config& c = ctx->cfg;
+    return wide_bwd_workspace_bytes(c.lattice == LBM_D3Q19, prec_of(c.mlp_prec),
+                                    (long long)c.batch * c.nx * c.ny * c.nz);
+  }
   return sizeof(float) * (size_t)bwd_blocks(ctx->ncu) * param_count(ctx->cfg);
 }
 
@@ -614,8 +670,6 @@ lbm_status lbm_step_backward(lbm_ctx* ctx, const float* A_n, const float* theta,
   if (!A_n || !lam_n1 || !lam_n) return fail(LBM_ERR_INVALID, "null array");
   if (lam_n == lam_n1 || lam_n == A_n)
     return fail(LBM_ERR_INVALID, "lam_n must not alias lam_n1 or A_n");
-  if (ctx->cfg.hidden != 0 && ctx->cfg.net != LBM_NET_TANH)
-    return fail(LBM_ERR_UNSUPPORTED, "the adjoint of LBM_NET_LEAKY_300_300_100 is not implemented");
   if (ctx->cfg.collision != LBM_COLLISION_BGK)
     return fail(LBM_ERR_UNSUPPORTED, "the adjoint of the Smagorinsky collision is not implemented");
   if (ctx->cfg.hidden != 0) {
@@ -623,6 +677,16 @@ lbm_status lbm_step_backward(lbm_ctx* ctx, const float* A_n, const float* theta,
     if (!ws) return fail(LBM_ERR_INVALID, "workspace is null");
     if (ws_bytes < lbm_workspace_bytes(ctx))
       return fail(LBM_ERR_WORKSPACE, "workspace smaller than lbm_workspace_bytes()");
+  }
+  if (ctx->cfg.hidden != 0 && ctx->cfg.net == LBM_NET_LEAKY_300_300_100) {
+    const lbm_config& c = ctx->cfg;
+    hipError_t e = wide_bwd_launch(c.lattice == LBM_D3Q19, prec_of(c.mlp_prec), stream, A_n, theta,
+                                   lam_n1, lam_n, dtheta, ws, ctx->wide_bidx, ctx->wide_bpacked,
+                                   grid_of(c), force_of(c), (float)c.rho0, (float)(1.0 / c.tau),
+                                   (float)(c.out_scale / c.tau));
+    if (e != hipSuccess)
+      return fail(LBM_ERR_HIP, std::string("wide-network adjoint: ") + hipGetErrorString(e));
+    return LBM_OK;
   }
   if (ctx->cfg.lattice == LBM_D2Q9)
     return run_backward<D2Q9>(ctx, A_n, theta, lam_n1, lam_n, dtheta, ws, stream);
