@@ -61,6 +61,8 @@ def parse():
     p.add_argument("--no-d3q19", action="store_true", help="skip the D3Q19 256^3 timing")
     p.add_argument("--no-wide", action="store_true",
                    help="skip the D3Q19 256^3 timing of the 19-300-300-100-19 network")
+    p.add_argument("--no-si", action="store_true",
+                   help="skip the timing of the SI's pipeline (DNS, wide-network training)")
     p.add_argument("--variants", default="bf16,fp16,fp32,bgk,smag")
     return p.parse_args()
 
@@ -258,6 +260,89 @@ def time_wide(torch, lbm, inputs, steps):
     return res
 
 
+# algorithmic flops per node of one adjoint step of the wide network: the
+# hidden layers recomputed, the input gradients of all four layers, and the
+# weight gradients
+WIDE_ADJ_FLOP_PER_LUP = 2 * (19 * 300 + 300 * 300 + 300 * 100) + 2 * WIDE_FLOP_PER_LUP
+
+
+def time_si_pipeline(torch, lbm, inputs):
+    """The SI's training recipe at its sizes, timed on synthetic states: the
+    forced D3Q19 128^3 DNS step (BGK, three-component sine force), and one
+    training epoch of the 19-300-300-100-19 network on the 32^3 coarse grid
+    (12 unrolled steps, checkpoint every 4, population loss on 512 nodes,
+    Adam), with the adjoint step alone."""
+    import numpy as np
+    from paper_2403_18466_amd import training
+    res = {}
+    n = 128
+    cfg = lbm.Config(lattice="D3Q19", nx=n, ny=n, nz=n, tau=0.5032,
+                     force_kind=lbm.LBM_FORCE_SINE3, force_k=1, force_amp=5e-6)
+    L = lbm.Lattice(cfg)
+    u = inputs.solenoidal_spectrum_velocity((n, n, n), 4.0, 0.04, seed=0).astype("float32")
+    A = L.init(torch.ones((1, n, n, n), device="cuda"), torch.from_numpy(u)[None].cuda())
+    B = torch.empty_like(A)
+    lbm.lbm_step(L.ctx, cfg, A, B, None, 10)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    lbm.lbm_step(L.ctx, cfg, A, B, None, 200)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 200
+    res["dns_128_forced_bgk"] = {"ms_per_step": ms, "mlups": n ** 3 / (ms * 1e-3) / 1e6}
+    L.close()
+    del A, B
+    m = 32
+    cc = lbm.Config(lattice="D3Q19", nx=m, ny=m, nz=m, tau=0.5008, force_kind=lbm.LBM_FORCE_SINE3,
+                    force_k=1, force_amp=2e-5, hidden=300, net="paper", mlp_prec="bf16")
+    L = lbm.Lattice(cc)
+    u = inputs.solenoidal_spectrum_velocity((m, m, m), 4.0, 0.04, seed=1).astype("float32")
+    A0 = L.init(torch.ones((1, m, m, m), device="cuda"), torch.from_numpy(u)[None].cuda())
+    T = L.step(A0, torch.zeros(L.n_param, device="cuda"), 12)
+    theta = torch.from_numpy(inputs.glorot_params_net(inputs.net_widths(19, 0, "paper"), 1)).cuda()
+    opt = training.Adam(theta, lr=1e-4, weight_decay=1e-6)
+    rng = np.random.default_rng(0)
+    nodes = torch.from_numpy(rng.choice(m ** 3, 512, replace=False).astype(np.int32)).cuda()
+
+    def epoch():
+        _, dth, _ = training.unrolled_loss_and_grad(
+            L, A0, theta, None, 12, 4, loss_fn=lambda A: L.loss_population_sse(A, T, nodes))
+        opt.step(dth)
+
+    for _ in range(3):
+        epoch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        epoch()
+    torch.cuda.synchronize()
+    res["wide_training_epoch_ms"] = (time.perf_counter() - t0) / 20 * 1e3
+    lam = torch.randn_like(A0)
+    lam0 = torch.empty_like(A0)
+    dth = torch.zeros(L.n_param, device="cuda")
+    ws = L.workspace()
+    lbm.lbm_step_backward(L.ctx, cc, A0, theta, lam, lam0, dth, ws)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(20):
+        lbm.lbm_step_backward(L.ctx, cc, A0, theta, lam, lam0, dth, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ams = e0.elapsed_time(e1) / 20
+    res["wide_adjoint_32"] = {"ms": ams, "mlups": m ** 3 / (ams * 1e-3) / 1e6,
+                              "tflops_algorithmic": WIDE_ADJ_FLOP_PER_LUP * m ** 3 / (ams * 1e-3) / 1e12}
+    L.close()
+    res["workload"] = ("SI recipe: forced D3Q19 128^3 DNS (tau 0.5032, F 5e-6); training epoch of "
+                       "the 19-300-300-100-19 network on 32^3 (tau' 0.5008, L_T 12, checkpoint 4, "
+                       "|S| 512, bf16, Adam) on synthetic states")
+    print(f"# SI pipeline: DNS 128^3 {res['dns_128_forced_bgk']['mlups']:.0f} MLUPS, wide training "
+          f"epoch {res['wide_training_epoch_ms']:.2f} ms, wide adjoint 32^3 {ams:.3f} ms",
+          file=sys.stderr, flush=True)
+    return res
+
+
 def cpu_baseline():
     """The FP64 oracle on a bounded sample of the same workload: one step of
     the same network on a 1024 x 1024 field (serial C, one host thread)."""
@@ -379,6 +464,8 @@ def main():
         result["d3q19_256"] = time_d3q19(torch, lbm, inputs, max(10, args.steps // 10))
     if not args.no_wide:
         result["wide_d3q19_256"] = time_wide(torch, lbm, inputs, max(10, args.steps // 10))
+    if not args.no_si:
+        result["si_pipeline"] = time_si_pipeline(torch, lbm, inputs)
     if not args.no_train:
         tr = {p: time_training(torch, lbm, inputs, p, 5) for p in ("bf16", "fp32")}
         for p, v in tr.items():

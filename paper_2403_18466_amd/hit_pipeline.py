@@ -225,19 +225,22 @@ def rollout(ds: HITDataset, theta, spec: TrainSpec, steps: int, every: int = 50,
 
 
 def main():
-    """The SI's pipeline at its sizes: 128^3 DNS, cg = 4, L_T = 12, the
-    19-64-64-19 tanh network (the adjoint of the SI's own 300-wide network is
-    not implemented), 8 samples."""
+    """The SI's pipeline at its sizes: 128^3 DNS, cg = 4, L_T = 12, 8
+    samples; --net paper trains the SI's own 19-300-300-100-19 LeakyReLU
+    network, --net tanh the 19-64-64-19 tanh one."""
     import argparse
     ap = argparse.ArgumentParser()
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--samples", type=int, default=8)
     ap.add_argument("--t0", type=int, default=50000)
     ap.add_argument("--rollout", type=int, default=2000)
+    ap.add_argument("--net", default="paper", choices=["paper", "tanh"])
+    ap.add_argument("--prec", default="bf16")
     args = ap.parse_args()
     ds = run_dns(DNSSpec(n_samples=args.samples, t0=args.t0), log=print)
     print(f"DNS: {ds.wall_s:.1f} s")
-    spec = TrainSpec(epochs=args.epochs)
+    spec = TrainSpec(epochs=args.epochs, net=args.net, prec=args.prec,
+                     hidden=300 if args.net == "paper" else 64)
     base = evaluate(ds, None, spec)
     theta, _ = train(ds, spec)
     trained = evaluate(ds, theta, spec)
