@@ -287,6 +287,32 @@ lbm_status lbm_loss_population_sse(lbm_ctx* ctx, const float* A, const float* ta
                                    const int32_t* nodes, int32_t n_nodes, double* loss,
                                    float* dLdA, hipStream_t stream);
 
+/* Eulerian structure functions (SI, eq. structure-fun-sm) of a velocity
+ * field u [batch][D][nz][ny][nx] of the context's grid, along the lattice
+ * axes: for l = 1..lmax and p = 1..pmax,
+ *   S[p-1][l-1]     = < (u_a(x + l e_a) - u_a(x))^p >,
+ *   S_abs[p-1][l-1] = < |u_a(x + l e_a) - u_a(x)|^p >,
+ * means over every node, field and axis a (the longitudinal increment,
+ * periodic).  S, S_abs: device float64 [pmax][lmax].  pmax <= 8, lmax <=
+ * the smallest grid size.  Increments and sums in float64, fixed order.  The
+ * context keeps a partial-sum buffer of lmax * 64 * 2 pmax doubles; a call
+ * that needs a larger one than before reallocates it (and waits for the
+ * device). */
+lbm_status lbm_structure_functions(lbm_ctx* ctx, const float* u, int32_t lmax, int32_t pmax,
+                                   double* S, double* S_abs, hipStream_t stream);
+
+/* Sums of the SI's moment-space analysis of a collision (D3Q19 only; the
+ * SI gives M for D3Q19).  A_n and A_n1 are consecutive states of lbm_step
+ * (pull-shifted, so A_n1(x) holds the post-collision populations of node
+ * x).  With pre = A_n gathered at x, f^eq and f^ext of pre (eq. feq,
+ * eq. fext) and the MRT matrix M:
+ *   m_diff = M (post - pre - f_ext),   m_neq = M (f_eq - pre),
+ * stats[i][0..4] (device float64 [19][5]) = sums over the nodes of m_neq_i,
+ * m_diff_i, m_neq_i^2, m_neq_i m_diff_i, m_diff_i^2.  A relaxation
+ * m_diff_i = m_neq_i / tau_i shows as the regression slope 1 / tau_i. */
+lbm_status lbm_mrt_moment_sums(lbm_ctx* ctx, const float* A_n, const float* A_n1, double* stats,
+                               hipStream_t stream);
+
 const char* lbm_status_str(lbm_status s);
 const char* lbm_last_error(void);
 

@@ -78,6 +78,9 @@ def _load():
             ("orc_step_adjoint", [cp, dp, dp, dp, dp, dp]),
             ("orc_loss_velocity_mse", [cp, dp, dp, dp, dp]),
             ("orc_subsample", [cp, dp, ctypes.c_int, dp]),
+            ("orc_structure_functions", [cp, dp, ctypes.c_int, ctypes.c_int, dp, dp]),
+            ("orc_mrt_moment_sums", [cp, dp, dp, dp]),
+            ("orc_mrt_matrix", [ctypes.POINTER(ctypes.c_int32)]),
             ("orc_loss_population_sse", [cp, dp, dp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
                                          dp, dp]),
         ]:
@@ -268,6 +271,36 @@ def loss_population_sse(cfg: Config, g_model, g_target, nodes, want_grad: bool =
         ctypes.byref(c), _ptr(gm), _ptr(gt), nd.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
         int(nd.size), ctypes.byref(loss), _ptr(grad)), "loss_population_sse")
     return loss.value, grad
+
+
+def structure_functions(cfg: Config, u, lmax: int, pmax: int):
+    """(S, S_abs), each [pmax][lmax]: the signed and absolute longitudinal
+    structure functions of the canonical velocity field u [B][D][nz][ny][nx]."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    assert u.shape == (cfg.batch, cfg.D, cfg.nz, cfg.ny, cfg.nx)
+    S = np.empty((pmax, lmax))
+    Sa = np.empty((pmax, lmax))
+    c = cfg._c()
+    _check(_load().orc_structure_functions(ctypes.byref(c), _ptr(u), lmax, pmax, _ptr(S), _ptr(Sa)),
+           "structure_functions")
+    return S, Sa
+
+
+def mrt_matrix():
+    M = np.empty(19 * 19, np.int32)
+    _load().orc_mrt_matrix(M.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return M.reshape(19, 19)
+
+
+def mrt_moment_sums(cfg: Config, g_n, g_n1):
+    """[19][5] sums of m_neq, m_diff, m_neq^2, m_neq m_diff, m_diff^2 over the
+    nodes for consecutive canonical states g_n, g_n1 (D3Q19)."""
+    a = np.ascontiguousarray(g_n, dtype=np.float64)
+    b = np.ascontiguousarray(g_n1, dtype=np.float64)
+    out = np.empty((19, 5))
+    c = cfg._c()
+    _check(_load().orc_mrt_moment_sums(ctypes.byref(c), _ptr(a), _ptr(b), _ptr(out)), "mrt_moment_sums")
+    return out
 
 
 def round_bf16(v: float) -> float:

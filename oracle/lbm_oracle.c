@@ -751,3 +751,130 @@ int orc_loss_population_sse(const orc_config *cfg, const double *g_model, const 
     *loss = acc;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Turbulence diagnostics                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Eulerian structure functions (SI, eq. structure-fun-sm) along the lattice
+ * axes: for l = 1..lmax and p = 1..pmax,
+ *   S[p-1][l-1]    = < (u_a(x + l e_a) - u_a(x))^p >,
+ *   Sabs[p-1][l-1] = < |u_a(x + l e_a) - u_a(x)|^p >,
+ * the mean over every node, field and axis a < D (periodic); the increment
+ * is the longitudinal one (along the separation).  u: canonical velocity
+ * field [B][D][nz][ny][nx]. */
+int orc_structure_functions(const orc_config *cfg, const double *u, int lmax, int pmax,
+                            double *S, double *Sabs) {
+    lattice_t L;
+    if (check_cfg(cfg, &L) || lmax < 1 || pmax < 1) return -1;
+    int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, D = L.D, N = nx * ny * nz;
+    int64_t dims[3] = {nx, ny, nz};
+    double count = (double)cfg->batch * N * D;
+    for (int l = 1; l <= lmax; ++l) {
+        for (int p = 0; p < pmax; ++p) {
+            S[p * lmax + l - 1] = 0.0;
+            Sabs[p * lmax + l - 1] = 0.0;
+        }
+        for (int64_t b = 0; b < cfg->batch; ++b)
+            for (int64_t a = 0; a < D; ++a)
+                for (int64_t z = 0; z < nz; ++z)
+                    for (int64_t y = 0; y < ny; ++y)
+                        for (int64_t x = 0; x < nx; ++x) {
+                            int64_t r[3] = {x, y, z};
+                            r[a] = (r[a] + l) % dims[a];
+                            double u0 = u[(b * D + a) * N + (z * ny + y) * nx + x];
+                            double u1 = u[(b * D + a) * N + (r[2] * ny + r[1]) * nx + r[0]];
+                            double d = u1 - u0, v = 1.0, va = 1.0;
+                            for (int p = 0; p < pmax; ++p) {
+                                v *= d;
+                                va *= fabs(d);
+                                S[p * lmax + l - 1] += v;
+                                Sabs[p * lmax + l - 1] += va;
+                            }
+                        }
+        for (int p = 0; p < pmax; ++p) {
+            S[p * lmax + l - 1] /= count;
+            Sabs[p * lmax + l - 1] /= count;
+        }
+    }
+    return 0;
+}
+
+/* The MRT moment matrix M of the SI (section on the physical
+ * interpretation of the model's action), for the D3Q19 order of Table S1;
+ * rows are (rho, e, eps, jx, qx, jy, qy, jz, qz, pxx, pixx, pww, piww, pxy,
+ * pyz, pxz, mx, my, mz). */
+static const int MRT_M[19][19] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-30, -11, -11, -11, -11, -11, -11, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8},
+    {12, -4, -4, -4, -4, -4, -4, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {0, -1, 0, 0, 0, 0, 1, -1, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 1},
+    {0, 4, 0, 0, 0, 0, -4, -1, -1, -1, -1, 0, 0, 0, 0, 1, 1, 1, 1},
+    {0, 0, -1, 0, 0, 1, 0, -1, 0, 0, 1, -1, -1, 1, 1, -1, 0, 0, 1},
+    {0, 0, 4, 0, 0, -4, 0, -1, 0, 0, 1, -1, -1, 1, 1, -1, 0, 0, 1},
+    {0, 0, 0, -1, 1, 0, 0, 0, -1, 1, 0, -1, 1, -1, 1, 0, -1, 1, 0},
+    {0, 0, 0, 4, -4, 0, 0, 0, -1, 1, 0, -1, 1, -1, 1, 0, -1, 1, 0},
+    {0, 2, -1, -1, -1, -1, 2, 1, 1, 1, 1, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, -4, 2, 2, 2, 2, -4, 1, 1, 1, 1, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 0, 1, -1, -1, 1, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, -1, 1},
+    {0, 0, -2, 2, 2, -2, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, -1, 1},
+    {0, 0, 0, 0, 0, 0, 0, 1, 0, 0, -1, 0, 0, 0, 0, -1, 0, 0, 1},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 0, 0, -1, 1, 0},
+    {0, 0, 0, 0, 0, 0, 0, -1, 1, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1},
+    {0, 0, 0, 0, 0, 0, 0, 1, 0, 0, -1, -1, -1, 1, 1, 1, 0, 0, -1},
+    {0, 0, 0, 0, 0, 0, 0, 0, -1, 1, 0, 1, -1, 1, -1, 0, -1, 1, 0},
+};
+
+int orc_mrt_matrix(int32_t *M) {
+    for (int i = 0; i < 19; ++i)
+        for (int q = 0; q < 19; ++q) M[i * 19 + q] = MRT_M[i][q];
+    return 0;
+}
+
+/* Regression sums of the SI's moment analysis (D3Q19): with f_pre the
+ * canonical state g_n, f_post the post-collision populations recovered from
+ * the next state by the inverse streaming, post_q(x) = g_n1_q(x + c_q),
+ *   m_diff = M (f_post - f_pre - f_ext),   m_neq = M (f_eq - f_pre),
+ * and for every moment i the sums over nodes and fields of
+ *   m_neq, m_diff, m_neq^2, m_neq m_diff, m_diff^2   -> stats[i][0..4]
+ * (a relaxation m_diff = m_neq / tau_i has slope 1 / tau_i). */
+int orc_mrt_moment_sums(const orc_config *cfg, const double *g_n, const double *g_n1,
+                        double *stats) {
+    lattice_t L;
+    if (check_cfg(cfg, &L) || L.Q != 19) return -1;
+    int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, N = nx * ny * nz;
+    for (int i = 0; i < 19 * 5; ++i) stats[i] = 0.0;
+    for (int64_t b = 0; b < cfg->batch; ++b)
+        for (int64_t z = 0; z < nz; ++z)
+            for (int64_t y = 0; y < ny; ++y)
+                for (int64_t x = 0; x < nx; ++x) {
+                    int64_t n = (z * ny + y) * nx + x;
+                    double pre[19], post[19], geq[19], fext[19], F[3], drho, j[3];
+                    for (int q = 0; q < 19; ++q) {
+                        pre[q] = g_n[(b * 19 + q) * N + n];
+                        int64_t xs = wrap(x + L.c[q][0], nx), ys = wrap(y + L.c[q][1], ny);
+                        int64_t zs = wrap(z + L.c[q][2], nz);
+                        post[q] = g_n1[(b * 19 + q) * N + (zs * ny + ys) * nx + xs];
+                    }
+                    node_moments(&L, pre, &drho, j);
+                    equilibrium_dev(&L, cfg->rho0, drho, j, geq);
+                    body_force(cfg, (int)x, (int)y, (int)z, F);
+                    double js[3] = {j[0] + F[0], j[1] + F[1], j[2] + F[2]}, e1[19];
+                    equilibrium_dev(&L, cfg->rho0, drho, js, e1);
+                    for (int q = 0; q < 19; ++q) fext[q] = e1[q] - geq[q];
+                    for (int i = 0; i < 19; ++i) {
+                        double md = 0.0, mn = 0.0;
+                        for (int q = 0; q < 19; ++q) {
+                            md += MRT_M[i][q] * (post[q] - pre[q] - fext[q]);
+                            mn += MRT_M[i][q] * (geq[q] - pre[q]);
+                        }
+                        stats[i * 5 + 0] += mn;
+                        stats[i * 5 + 1] += md;
+                        stats[i * 5 + 2] += mn * mn;
+                        stats[i * 5 + 3] += mn * md;
+                        stats[i * 5 + 4] += md * md;
+                    }
+                }
+    return 0;
+}

@@ -12,6 +12,7 @@
 
 #include "kernels_aux.hpp"
 #include "kernels_bwd.hpp"
+#include "kernels_diag.hpp"
 #include "kernels_fwd.hpp"
 #include "lbm.h"
 #include "wide.hpp"
@@ -34,6 +35,9 @@ struct lbm_ctx {
   // its adjoint: gather table and packed padded W, W^T and bias vectors
   int* wide_bidx;
   unsigned char* wide_bpacked;
+  // diagnostics partials, grown on demand
+  double* diag;
+  size_t diag_bytes;
 };
 
 namespace {
@@ -500,6 +504,8 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   ctx->wide_nw = ctx->wide_nb = 0;
   ctx->wide_bidx = nullptr;
   ctx->wide_bpacked = nullptr;
+  ctx->diag = nullptr;
+  ctx->diag_bytes = 0;
   size_t bytes = sizeof(double) * 3 * MOM_BLOCKS * (size_t)cfg->batch;
   hipError_t e = hipMalloc(&ctx->partial, bytes);
   if (e != hipSuccess) {
@@ -548,6 +554,7 @@ lbm_status lbm_destroy(lbm_ctx* ctx) {
   if (ctx->wide_packed) (void)hipFree(ctx->wide_packed);
   if (ctx->wide_bidx) (void)hipFree(ctx->wide_bidx);
   if (ctx->wide_bpacked) (void)hipFree(ctx->wide_bpacked);
+  if (ctx->diag) (void)hipFree(ctx->diag);
   delete ctx;
   return LBM_OK;
   LBM_GUARD_END
@@ -792,6 +799,71 @@ lbm_status lbm_loss_population_sse(lbm_ctx* ctx, const float* A, const float* ta
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, stream, ctx->partial, nblk, 1.0,
                      loss);
   LBM_LAUNCHED("sum_partials_kernel");
+  return LBM_OK;
+  LBM_GUARD_END
+}
+
+namespace {
+// The context's diagnostics buffer of at least `bytes` (a reallocation waits
+// for the device).
+lbm_status diag_buffer(lbm_ctx* ctx, size_t bytes) {
+  if (ctx->diag_bytes >= bytes) return LBM_OK;
+  if (ctx->diag) {
+    LBM_HIP(hipDeviceSynchronize());
+    LBM_HIP(hipFree(ctx->diag));
+    ctx->diag = nullptr;
+    ctx->diag_bytes = 0;
+  }
+  LBM_HIP(hipMalloc(&ctx->diag, bytes));
+  ctx->diag_bytes = bytes;
+  return LBM_OK;
+}
+}  // namespace
+
+lbm_status lbm_structure_functions(lbm_ctx* ctx, const float* u, int32_t lmax, int32_t pmax,
+                                   double* S, double* S_abs, hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  lbm_status st = check_ctx(ctx);
+  if (st != LBM_OK) return st;
+  if (!u || !S || !S_abs) return fail(LBM_ERR_INVALID, "null array");
+  if (pmax < 1 || pmax > SF_PMAX) return fail(LBM_ERR_INVALID, "pmax must be in 1..8");
+  const lbm_config& c = ctx->cfg;
+  int lim = c.nx < c.ny ? c.nx : c.ny;
+  if (c.lattice == LBM_D3Q19 && c.nz < lim) lim = c.nz;
+  if (lmax < 1 || lmax > lim) return fail(LBM_ERR_INVALID, "lmax must be in 1..min(grid sizes)");
+  st = diag_buffer(ctx, sizeof(double) * (size_t)lmax * DIAG_BLOCKS * 2 * pmax);
+  if (st != LBM_OK) return st;
+  Grid G = grid_of(c);
+  dim3 grid(DIAG_BLOCKS, (unsigned)lmax);
+  if (c.lattice == LBM_D2Q9)
+    hipLaunchKernelGGL(structure_kernel<2>, grid, dim3(256), 0, stream, u, G, pmax, ctx->diag);
+  else
+    hipLaunchKernelGGL(structure_kernel<3>, grid, dim3(256), 0, stream, u, G, pmax, ctx->diag);
+  LBM_LAUNCHED("structure_kernel");
+  const double count = (double)G.plane * G.batch * lattice_d(c.lattice);
+  hipLaunchKernelGGL(structure_reduce_kernel, dim3(blocks_for((long long)lmax * 2 * pmax)), dim3(256),
+                     0, stream, ctx->diag, DIAG_BLOCKS, lmax, pmax, 1.0 / count, S, S_abs);
+  LBM_LAUNCHED("structure_reduce_kernel");
+  return LBM_OK;
+  LBM_GUARD_END
+}
+
+lbm_status lbm_mrt_moment_sums(lbm_ctx* ctx, const float* A_n, const float* A_n1, double* stats,
+                               hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  lbm_status st = check_ctx(ctx);
+  if (st != LBM_OK) return st;
+  if (!A_n || !A_n1 || !stats) return fail(LBM_ERR_INVALID, "null array");
+  if (ctx->cfg.lattice != LBM_D3Q19)
+    return fail(LBM_ERR_UNSUPPORTED, "the moment matrix M is given for D3Q19 only");
+  st = diag_buffer(ctx, sizeof(double) * 19 * DIAG_BLOCKS * 5);
+  if (st != LBM_OK) return st;
+  Grid G = grid_of(ctx->cfg);
+  hipLaunchKernelGGL(mrt_sums_kernel, dim3(DIAG_BLOCKS, 19), dim3(256), 0, stream, A_n, A_n1, G,
+                     force_of(ctx->cfg), (float)ctx->cfg.rho0, ctx->diag);
+  LBM_LAUNCHED("mrt_sums_kernel");
+  hipLaunchKernelGGL(mrt_reduce_kernel, dim3(1), dim3(128), 0, stream, ctx->diag, DIAG_BLOCKS, stats);
+  LBM_LAUNCHED("mrt_reduce_kernel");
   return LBM_OK;
   LBM_GUARD_END
 }

@@ -224,6 +224,29 @@ def rollout(ds: HITDataset, theta, spec: TrainSpec, steps: int, every: int = 50,
     return out
 
 
+def diagnose(ds: HITDataset, theta, spec: TrainSpec, steps: int, device="cuda"):
+    """The SI's evaluation quantities after `steps` coarse steps from the
+    first sample, for BGK at tau' (theta None), the trained network, or the
+    Smagorinsky collision (theta == "smagorinsky", C_s = 0.17): longitudinal
+    structure functions (S, S_abs) up to p = 6 and l = L'/2, and the
+    effective relaxation time of each MRT moment over the last step."""
+    from . import diagnostics
+    net = {}
+    if isinstance(theta, str):
+        net = dict(collision="smagorinsky", smag_cs=0.17)
+        theta = None
+    elif theta is not None:
+        net = dict(hidden=spec.hidden, net=spec.net, mlp_prec=spec.prec, out_scale=spec.out_scale)
+    cfg = coarse_config(ds.spec, **net)
+    L = lbm.Lattice(cfg, device)
+    A = L.step(ds.starts[0], theta, steps - 1) if steps > 1 else ds.starts[0].clone()
+    A1 = L.step(A, theta, 1)
+    S, Sa = diagnostics.structure_functions(L, A1, cfg.nx // 2, 6)
+    tau = diagnostics.mrt_relaxation(L, A, A1)
+    L.close()
+    return S, Sa, tau
+
+
 def main():
     """The SI's pipeline at its sizes: 128^3 DNS, cg = 4, L_T = 12, 8
     samples; --net paper trains the SI's own 19-300-300-100-19 LeakyReLU
@@ -250,6 +273,19 @@ def main():
         traj = rollout(ds, th, spec, args.rollout, every=max(1, args.rollout // 8))
         print(f"free run, {name}: " + ", ".join(f"{t}: KE {e:.3e} ({b} non-finite)"
                                                 for t, e, b in traj))
+    from . import diagnostics
+    cfg = coarse_config(ds.spec)
+    Lc = lbm.Lattice(cfg)
+    S_dns, Sa_dns = diagnostics.structure_functions(Lc, ds.targets[0], cfg.nx // 2, 6)
+    Lc.close()
+    print("structure functions S_abs^p(l), p = 2, 3, 6, l = 1, 2, 4, 8 "
+          "(filtered DNS, then the models after 200 coarse steps):")
+    print("  DNS:   " + " ".join(f"{Sa_dns[p - 1, l - 1]:.3e}" for p in (2, 3, 6) for l in (1, 2, 4, 8)))
+    for name, th in (("trained", theta), ("Smag.", "smagorinsky")):
+        S, Sa, tau = diagnose(ds, th, spec, 200)
+        print(f"  {name}: " + " ".join(f"{Sa[p - 1, l - 1]:.3e}" for p in (2, 3, 6) for l in (1, 2, 4, 8)))
+        print(f"  {name} effective relaxation times: " +
+              ", ".join(f"{k} {v[0]:.4f}" for k, v in tau.items() if v[0] == v[0]))
 
 
 if __name__ == "__main__":

@@ -34,7 +34,8 @@ EXPORTS = (
     "lbm_create", "lbm_destroy", "lbm_state_elems", "lbm_param_elems", "lbm_workspace_bytes",
     "lbm_lattice_tables", "lbm_init", "lbm_step", "lbm_moments", "lbm_shift",
     "lbm_step_backward", "lbm_loss_velocity_mse", "lbm_adam", "lbm_box_filter",
-    "lbm_subsample", "lbm_loss_population_sse", "lbm_status_str", "lbm_last_error",
+    "lbm_subsample", "lbm_loss_population_sse", "lbm_structure_functions",
+    "lbm_mrt_moment_sums", "lbm_status_str", "lbm_last_error",
 )
 
 
@@ -87,6 +88,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_box_filter": ([vp, vp, i32, i32, i32, i32, i32, i32, vp], ctypes.c_int),
         "lbm_subsample": ([i32, vp, vp, i32, i32, i32, i32, i32, vp], ctypes.c_int),
         "lbm_loss_population_sse": ([vp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
+        "lbm_structure_functions": ([vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
+        "lbm_mrt_moment_sums": ([vp, vp, vp, vp, vp], ctypes.c_int),
         "lbm_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "lbm_last_error": ([], ctypes.c_char_p),
     }
@@ -307,6 +310,21 @@ def lbm_loss_population_sse(ctx, cfg: Config, A, target, nodes, loss, dLdA=None,
         _ptr(loss, torch.float64, 1, "loss"),
         _ptr(dLdA, torch.float32, n, "dLdA", allow_none=True), _stream(stream)),
         "lbm_loss_population_sse")
+
+
+def lbm_structure_functions(ctx, cfg: Config, u, lmax, pmax, S, S_abs, stream=None):
+    n = cfg.batch * cfg.D * cfg.nx * cfg.ny * cfg.nz
+    _check(load_library().lbm_structure_functions(
+        ctx, _ptr(u, torch.float32, n, "u"), int(lmax), int(pmax),
+        _ptr(S, torch.float64, lmax * pmax, "S"), _ptr(S_abs, torch.float64, lmax * pmax, "S_abs"),
+        _stream(stream)), "lbm_structure_functions")
+
+
+def lbm_mrt_moment_sums(ctx, A_n, A_n1, stats, stream=None):
+    n = lbm_state_elems(ctx)
+    _check(load_library().lbm_mrt_moment_sums(
+        ctx, _ptr(A_n, torch.float32, n, "A_n"), _ptr(A_n1, torch.float32, n, "A_n1"),
+        _ptr(stats, torch.float64, 95, "stats"), _stream(stream)), "lbm_mrt_moment_sums")
 
 
 # ------------------------------------------------------------ convenience

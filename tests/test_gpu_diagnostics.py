@@ -1,0 +1,75 @@
+"""GPU parity of the diagnostics against the FP64 oracle: structure
+functions of a velocity field, and the sums of the moment-space analysis
+for one step of each collision (BGK, the two networks, Smagorinsky)."""
+import numpy as np
+import pytest
+
+import oracle
+from lbm_cases import lib_config, params, random_state, to_canonical, to_shifted
+from paper_2403_18466_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_18466_amd import lbm as m
+    m.load_library()
+    return m
+
+
+@pytest.mark.parametrize("lat,shape", [("D2Q9", (1, 30, 70)), ("D3Q19", (6, 7, 9))])
+def test_structure_functions(lbm, lat, shape):
+    nz, ny, nx = shape
+    ocfg = oracle.Config(lattice=lat, nx=nx, ny=ny, nz=nz, batch=2)
+    u = np.random.default_rng(91).normal(0, 0.05, (2, ocfg.D, nz, ny, nx)).astype(np.float32)
+    lmax, pmax = min(shape[1:] if lat == "D2Q9" else shape), 6
+    want, wabs = oracle.structure_functions(ocfg, u.astype(np.float64), lmax, pmax)
+    L = lbm.Lattice(lib_config(ocfg))
+    S = torch.empty((pmax, lmax), dtype=torch.float64, device="cuda")
+    Sa = torch.empty_like(S)
+    lbm.lbm_structure_functions(L.ctx, L.cfg, torch.from_numpy(u).cuda(), lmax, pmax, S, Sa)
+    got, gabs = S.cpu().numpy(), Sa.cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(wabs).max(axis=1, keepdims=True).max()
+    assert np.all(np.abs(gabs - wabs) <= 1e-12 * wabs)
+    L.close()
+
+
+@pytest.mark.parametrize("kind", ["bgk", "tanh", "paper", "smagorinsky", "bgk-forced"])
+def test_mrt_moment_sums(lbm, kind):
+    from paper_2403_18466_amd import diagnostics
+    kw = dict(lattice="D3Q19", nx=9, ny=6, nz=5, batch=2, tau=0.55)
+    theta = None
+    if kind == "tanh":
+        kw.update(hidden=64, out_scale=0.25)
+        theta = params(19, 64, seed=92, kind="random")
+    elif kind == "paper":
+        kw.update(hidden=300, net="paper", out_scale=0.25)
+        theta = inputs.random_params_net(inputs.net_widths(19, 0, "paper"), 93, scale=0.05)
+    elif kind == "smagorinsky":
+        kw.update(collision="smagorinsky", smag_cs=0.17)
+    elif kind == "bgk-forced":
+        kw.update(force_kind=2, force_amp=1e-3, force_k=1)
+    ocfg = oracle.Config(**kw)
+    g = random_state(ocfg, 94, 0.03)
+    L = lbm.Lattice(lib_config(ocfg))
+    A = torch.from_numpy(to_shifted(g, "D3Q19").astype(np.float32)).cuda()
+    th = torch.from_numpy(theta).cuda() if theta is not None else None
+    A1 = L.step(A, th, 1)
+    stats = torch.empty((19, 5), dtype=torch.float64, device="cuda")
+    lbm.lbm_mrt_moment_sums(L.ctx, A, A1, stats)
+    got = stats.cpu().numpy()
+    torch.cuda.synchronize()
+    g1 = to_canonical(A1.cpu().numpy().astype(np.float64), "D3Q19")
+    want = oracle.mrt_moment_sums(ocfg, g.astype(np.float32).astype(np.float64), g1)
+    scale = np.abs(want).max(axis=1, keepdims=True) + 1e-30
+    assert np.abs(got - want).max() <= 1e-5 * scale.max()
+    res = diagnostics.relaxation_from_sums(got, 2 * 9 * 6 * 5)
+    if kind.startswith("bgk"):
+        for name in ("pxy", "pxx", "e", "qx", "mx"):
+            assert abs(res[name][0] - 0.55) < 1e-4, (name, res[name])
+    print(kind, {k: round(v[0], 4) for k, v in res.items() if not np.isnan(v[0])})
+    L.close()
