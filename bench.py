@@ -37,10 +37,10 @@ SIMD_CYCLES = 256 * 4 * 2.4e9  # 256 CUs x 4 SIMDs x 2.4 GHz
 FP32_LANES, TRANS_LANES = 16, 8
 TRANS_PEAK = SIMD_CYCLES * TRANS_LANES
 # Minimal ALU work of the activation per LUP: 128 tanh, each one exp2 + one
-# reciprocal (transcendental) and three FP32 ops (argument scale, 1 + e,
-# 1 - 2r), plus one packed conversion per two activations to the operand
-# format.  In SIMD-cycles per LUP:
-ACT_CYCLES_PER_LUP = (TANH_PER_LUP * (TRANS_PER_TANH / TRANS_LANES + 3 / FP32_LANES)
+# reciprocal (transcendental) and two FP32 ops (1 + e, 1 - 2r; the argument
+# scale 2 log2 e rides in the bf16 weights), plus one packed conversion per
+# two activations to the operand format.  In SIMD-cycles per LUP:
+ACT_CYCLES_PER_LUP = (TANH_PER_LUP * (TRANS_PER_TANH / TRANS_LANES + 2 / FP32_LANES)
                       + TANH_PER_LUP / 2 / FP32_LANES)
 ACT_PEAK_LUPS = SIMD_CYCLES / ACT_CYCLES_PER_LUP
 
@@ -48,7 +48,7 @@ ACT_PEAK_LUPS = SIMD_CYCLES / ACT_CYCLES_PER_LUP
 # HBM bytes per launch of the bf16 step from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # each scaled by the factor a plain copy of known size gives (2.000 / 1.000);
 # None until taken for the current kernel (profiles/).
-TRAFFIC_BYTES = 1.2230e9
+TRAFFIC_BYTES = None
 
 
 def parse():
@@ -410,7 +410,7 @@ def main():
         "bound": "alu",
         "achieved": lups / 1e9,
         "peak": ACT_PEAK_LUPS / 1e9,
-        "unit": "GLUP/s (activation ALU ceiling: 128 tanh x (2 transcendental + 3 FP32) + "
+        "unit": "GLUP/s (activation ALU ceiling: 128 tanh x (2 transcendental + 2 FP32) + "
                 "64 conversions per LUP at 8 / 16 lanes per clock per SIMD)",
         "frac": lups / ACT_PEAK_LUPS,
         "traffic": TRAFFIC_BYTES,

@@ -189,6 +189,20 @@ static double quantise(int quant, double v) {
     return v;
 }
 
+/* The weight a reduced-precision network reads.  A tanh is evaluated as
+ * 1 - 2 / (1 + 2^(c z)) with c = 2 log2(e); the tanh layers carry c (as a
+ * float32) in their operands, so the operand is the float32 product c w
+ * rounded to the format and the weight in effect is that divided by c.
+ * Other layers round w itself. */
+static const float TANH_SCALE = 2.8853900817779268f;
+
+static double qweight(int quant, int scaled, double w) {
+    if (!quant) return w;
+    if (!scaled) return quantise(quant, w);
+    double c = (double)TANH_SCALE;
+    return quantise(quant, (double)(float)(c * w)) / c;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Per-node physics                                                          */
 /* ------------------------------------------------------------------------ */
@@ -278,7 +292,8 @@ static double activation_slope(int leaky, double a, double t) {
 /* The MLP of the SI: linear layers with the hidden activation after every
  * layer but the last.  In the emulated reduced-precision mode the network
  * input, the weights, the layer-1 bias and every hidden activation are
- * rounded; the other biases and all sums stay exact. */
+ * rounded (the weights and layer-1 bias of tanh layers as in qweight); the
+ * other biases and all sums stay exact. */
 static void mlp_forward(const orc_config *cfg, const net_shape *n, const double *theta,
                         node_fwd *s) {
     int qt = cfg->quant;
@@ -288,9 +303,10 @@ static void mlp_forward(const orc_config *cfg, const net_shape *n, const double 
     for (int l = 0; l < n->nl; ++l) {
         int nin = n->width[l], nout = n->width[l + 1];
         const double *b = W + (int64_t)nout * nin;
+        int scaled = !n->leaky && l + 1 < n->nl;
         for (int o = 0; o < nout; ++o) {
-            double a = l == 0 ? quantise(qt, b[o]) : b[o];
-            for (int i = 0; i < nin; ++i) a += quantise(qt, W[(int64_t)o * nin + i]) * in[i];
+            double a = l == 0 ? qweight(qt, scaled, b[o]) : b[o];
+            for (int i = 0; i < nin; ++i) a += qweight(qt, scaled, W[(int64_t)o * nin + i]) * in[i];
             if (l + 1 < n->nl) {
                 s->pre[l][o] = a;
                 s->t[l][o] = activation(n->leaky, a);
@@ -595,9 +611,10 @@ static void collide_node_adjoint(const orc_config *cfg, const lattice_t *L, cons
                 db[o] += dz[o];
                 for (int i = 0; i < nin; ++i) dW[(int64_t)o * nin + i] += dz[o] * in[i];
             }
+            int scaled = !n.leaky && l + 1 < n.nl;
             for (int i = 0; i < nin; ++i) {
                 double d = 0.0;
-                for (int o = 0; o < nout; ++o) d += quantise(qt, W[(int64_t)o * nin + i]) * dz[o];
+                for (int o = 0; o < nout; ++o) d += qweight(qt, scaled, W[(int64_t)o * nin + i]) * dz[o];
                 din[i] = d;
             }
             if (l > 0) {

@@ -186,6 +186,9 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
   // Block-shared transposed weight fragments for the backward contractions.
+  // W2 and W1 are the tanh layers: for bf16 / fp16 their fragments hold
+  // c W rounded, like the forward's, and the products are scaled back by 1/c.
+  constexpr float sc = tanh_weight_scale<P>();
   for (int e = threadIdx.x; e < BL::NF * 64; e += 256) {
     const int f = e >> 6, l = e & 63, g = l >> 4, i = l & 15;
     f4 v;
@@ -199,13 +202,13 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
     } else if (f < BL::NF3 + BL::NF2) {  // W2^T: row h = 16 ob + i, k = o = 16 c + 4 g + r
       const int ff = f - BL::NF3, ob = ff / S::HB, c = ff % S::HB;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = theta[S::oW2 + (16 * c + 4 * g + r) * H + 16 * ob + i];
+      for (int r = 0; r < 4; ++r) v[r] = sc * theta[S::oW2 + (16 * c + 4 * g + r) * H + 16 * ob + i];
     } else {  // W1^T: row k = 16 c + i (input index), k' = o = 16 ob + 4 g + r
       const int ff = f - BL::NF3 - BL::NF2, c = ff / S::HB, ob = ff % S::HB;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int k = 16 * c + i, o = 16 * ob + 4 * g + r;
-        v[r] = k < Q ? theta[S::oW1 + o * Q + k] : 0.f;
+        v[r] = k < Q ? sc * theta[S::oW1 + o * Q + k] : 0.f;
       }
     }
     wbk[e] = to_frag<P>(v);
@@ -341,6 +344,7 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
 #pragma unroll
       for (int ob = 0; ob < S::HB; ++ob) {
         f4 a = mma_row_lds<P, S::HB>(f4{0.f, 0.f, 0.f, 0.f}, W2T + ob * S::HB * 64 + lane, d2f);
+        if constexpr (sc != 1.f) a = a * (1.f / sc);
         d1[ob] = a * (1.f - t1[ob] * t1[ob]);
         d1f[ob] = to_frag<P>(d1[ob]);
       }
@@ -382,6 +386,7 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
 #pragma unroll
       for (int c = 0; c < S::KX; ++c) {
         f4 a = mma_row_lds<P, S::HB>(f4{0.f, 0.f, 0.f, 0.f}, W1T + c * S::HB * 64 + lane, d1f);
+        if constexpr (sc != 1.f) a = a * (1.f / sc);
         *reinterpret_cast<f4*>(D + nrow * BL::SD + 16 * c + 4 * lg) = a;
       }
     }

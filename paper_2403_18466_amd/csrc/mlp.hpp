@@ -159,15 +159,33 @@ __device__ inline float tanh_accurate(float z) {
   return __builtin_fabsf(z) < 0.55f ? small : tanh_fast(z);
 }
 
-// Activation of the precision: the float32 network needs the accurate tanh
-// to stay within 1e-5 of float64 over hundreds of steps; the bf16 / fp16
-// networks round the activation to 8 / 11 bits, far above the fast form's
-// ~1e-7 absolute error.
+// Scale of the tanh argument on the hardware exp2: e^{2z} = 2^{c z},
+// c = 2 log2(e).  The bf16 / fp16 networks carry it in the weights and the
+// bias of the two tanh layers (the operand then holds c W rounded to the
+// format), so their activation starts at exp2 of the accumulator.
+constexpr float kTanhScale = 2.8853900817779268f;
+
+// tanh(z) from v = c z: 1 - 2 / (1 + 2^v).
+__device__ inline float tanh_prescaled(float v) {
+  return __builtin_fmaf(-2.f, __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(v)), 1.f);
+}
+
+// Scale applied to the tanh layers' weights for precision P.
+template <int P>
+__device__ constexpr float tanh_weight_scale() {
+  return P == P_F32 ? 1.f : kTanhScale;
+}
+
+// Activation of the precision, from the accumulator of a tanh layer: the
+// float32 network needs the accurate tanh to stay within 1e-5 of float64
+// over hundreds of steps; the bf16 / fp16 networks round the activation to
+// 8 / 11 bits, far above the fast form's ~1e-7 absolute error, and their
+// accumulator is already c z.
 template <int P>
 __device__ inline f4 tanh4(f4 v) {
   f4 r;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) r[k] = P == P_F32 ? tanh_accurate(v[k]) : tanh_fast(v[k]);
+  for (int k = 0; k < 4; ++k) r[k] = P == P_F32 ? tanh_accurate(v[k]) : tanh_prescaled(v[k]);
   return r;
 }
 
@@ -186,7 +204,8 @@ struct Shape {
 // Weight fragments of one wave, resident in registers for the whole kernel.
 // Layer 1 carries its bias as an extra input column (index Q, fed by a
 // constant 1 in the input), layers 2 and 3 start their accumulators at the
-// bias.
+// bias.  For bf16 / fp16 the two tanh layers (weights, layer-1 bias column
+// and b2) are scaled by c = 2 log2(e) before rounding, see tanh4.
 template <int P, class S>
 struct Weights {
   using F = typename Frag<P>::T;
@@ -199,6 +218,7 @@ struct Weights {
   // lane-local A-operand entry: row o, k = 16 c + 4 g + r
   __device__ inline void load(const float* __restrict__ th) {
     const int l = threadIdx.x & 63, g = l >> 4, i = l & 15;
+    constexpr float sc = tanh_weight_scale<P>();
 #pragma unroll
     for (int ob = 0; ob < S::HB; ++ob) {
       const int o = 16 * ob + i;
@@ -208,7 +228,7 @@ struct Weights {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           int k = 16 * c + 4 * g + r;
-          v[r] = k < S::Q ? th[S::oW1 + o * S::Q + k] : (k == S::Q ? th[S::ob1 + o] : 0.f);
+          v[r] = sc * (k < S::Q ? th[S::oW1 + o * S::Q + k] : (k == S::Q ? th[S::ob1 + o] : 0.f));
         }
         w1[ob][c] = to_frag<P>(v);
       }
@@ -216,11 +236,11 @@ struct Weights {
       for (int c = 0; c < S::HB; ++c) {
         f4 v;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = th[S::oW2 + o * S::H + 16 * c + 4 * g + r];
+        for (int r = 0; r < 4; ++r) v[r] = sc * th[S::oW2 + o * S::H + 16 * c + 4 * g + r];
         w2[ob][c] = to_frag<P>(v);
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) b2[ob][r] = th[S::ob2 + 16 * ob + 4 * g + r];
+      for (int r = 0; r < 4; ++r) b2[ob][r] = sc * th[S::ob2 + 16 * ob + 4 * g + r];
     }
 #pragma unroll
     for (int ob = 0; ob < S::QB; ++ob) {

@@ -583,7 +583,8 @@ def test_velocity_mse_loss_definition():
 # P14: emulated reduced-precision network.  The same collision written as
 # matrix products with torch's own float32 -> bfloat16 / float16 conversions
 # at the stated rounding points (input, both hidden activations, weights and
-# the layer-1 bias, which the network reads as one more input column).
+# the layer-1 bias, which the network reads as one more input column; the
+# tanh layers' operands are the float32 products c W, c = 2 log2 e).
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("quant", ["bf16", "fp16"])
@@ -619,9 +620,15 @@ def test_emulated_quantisation_points(quant):
     b2 = theta[o:o + H]; o += H
     W3 = theta[o:o + 9 * H].reshape(9, H); o += 9 * H
     b3 = theta[o:o + 9]
+    # the tanh layers hold c W in the operand: float32 product, then rounded
+    c = float(np.float32(2.8853900817779268))
+
+    def rnd_scaled(a):
+        return rnd((np.float32(c) * np.asarray(a, np.float32)).astype(np.float64)) / c
+
     x0 = rnd_act(g.reshape(9, -1))
-    h1 = rnd_act(np.tanh(rnd(W1) @ x0 + rnd(b1)[:, None]))
-    h2 = rnd_act(np.tanh(rnd(W2) @ h1 + b2[:, None]))
+    h1 = rnd_act(np.tanh(rnd_scaled(W1) @ x0 + rnd_scaled(b1)[:, None]))
+    h2 = rnd_act(np.tanh(rnd_scaled(W2) @ h1 + b2[:, None]))
     y = rnd(W3) @ h2 + b3[:, None]
     P = brute.projector()
     want = (oracle.collide(cfg_0, g).reshape(9, -1) + P @ ((s / tau) * y)).reshape(g.shape)
