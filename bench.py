@@ -90,20 +90,29 @@ def time_variant(torch, lbm, inputs, prec, hidden, steps, warmup, A0, collision=
     if warmup > 0:
         lbm.lbm_step(L.ctx, cfg, A, B, theta, warmup, stream)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    # the timed steps run as up to 5 back-to-back chunks on one stream, with
+    # an event between chunks: the total gives ms/step, the chunks the spread
+    nchunk = min(5, steps)
+    sizes = [steps // nchunk + (1 if i < steps % nchunk else 0) for i in range(nchunk)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nchunk + 1)]
     t0 = time.perf_counter()
-    e0.record(stream)
-    out = lbm.lbm_step(L.ctx, cfg, A, B, theta, steps, stream)
-    e1.record(stream)
+    ev[0].record(stream)
+    src, other = A, B
+    for i, k in enumerate(sizes):
+        out = lbm.lbm_step(L.ctx, cfg, src, other, theta, k, stream)
+        src, other = (out, B if out is A else A)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / steps
+    ms = ev[0].elapsed_time(ev[-1]) / steps
+    chunk = sorted(ev[i].elapsed_time(ev[i + 1]) / k for i, k in enumerate(sizes))
     _, _, diag = L.moments(out)
     torch.cuda.synchronize()
     d = diag.cpu().numpy()[0]
     L.close()
     return {"ms_per_step": ms, "mlups": N * N / (ms * 1e-3) / 1e6, "wall_s": wall,
+            "chunk_ms_per_step": {"median": chunk[len(chunk) // 2], "min": chunk[0],
+                                  "max": chunk[-1], "chunks": nchunk},
             "mass": float(d[0]), "kinetic_energy": float(d[1]), "nonfinite": int(d[2])}
 
 
@@ -443,6 +452,7 @@ def main():
         "roofline": roofline,
         "variants": {k: {"mlups": v["mlups"], "ms_per_step": v["ms_per_step"],
                          "hbm_frac": BYTES_PER_LUP * N * N / (v["ms_per_step"] * 1e-3) / HBM_PEAK,
+                         "chunk_ms_per_step": v["chunk_ms_per_step"],
                          "nonfinite": v["nonfinite"]} for k, v in variants.items()},
     }
     if "fp32" in variants:

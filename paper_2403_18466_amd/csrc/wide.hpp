@@ -156,73 +156,39 @@ __device__ inline typename Frag<P>::T lds_single(const unsigned char* p, int lan
     return *reinterpret_cast<const u2*>(p + lane * 8);
 }
 
-// acc[n] += W(tile) x[n] over KC chunks of a tile whose units start at p.
-template <int P, int KC, int NT>
-__device__ inline void tile_row(const unsigned char* p, int lane, f4 (&acc)[NT],
-                                const typename Frag<P>::T (*x)[NT]) {
-  using WL = WideLayout<9, P>;  // only CHUNK is used, which does not depend on Q
-  constexpr int CH = WL::CHUNK;
-#pragma unroll
-  for (int c = 0; c + 1 < KC; c += 2) {
-    typename Frag<P>::T a0, a1;
-    lds_pair<P>(p + c * CH, lane, a0, a1);
-#pragma unroll
-    for (int n = 0; n < NT; ++n) acc[n] = mma_pair<P>(acc[n], a0, a1, x[c][n], x[c + 1][n]);
-  }
-  if constexpr (KC % 2 == 1) {
-    const typename Frag<P>::T a = lds_single<P>(p + (KC - 1) * CH, lane);
-#pragma unroll
-    for (int n = 0; n < NT; ++n) acc[n] = mma_chunk<P>(acc[n], a, x[KC - 1][n]);
-  }
+// The A fragments of one staged unit: a chunk pair (a0, a1) or a single
+// chunk (a0).
+template <int P>
+struct Unit {
+  typename Frag<P>::T a0, a1;
+};
+
+template <int P, bool PAIR>
+__device__ inline void lds_unit(const unsigned char* p, int lane, Unit<P>& f) {
+  if constexpr (PAIR)
+    lds_pair<P>(p, lane, f.a0, f.a1);
+  else
+    f.a0 = lds_single<P>(p, lane);
 }
 
-// acc[j][n] += W(tile j) x[n] for the GT tiles whose units start at
-// p + j * KC * CHUNK, over K chunks 0..KC-1: the fragments of the next chunk
-// pair of every tile are read from LDS before the MFMAs of the current pair
-// are issued, so LDS latency overlaps matrix-core work.
-template <int P, int KC, int NT, int GT>
-__device__ inline void tiles_row(const unsigned char* p, int lane, f4 (&acc)[GT][NT],
-                                 const typename Frag<P>::T (*x)[NT]) {
-  using Fr = typename Frag<P>::T;
-  constexpr int CH = WideLayout<9, P>::CHUNK;
-  constexpr int NP = KC / 2;
-  Fr a0[GT], a1[GT];
-  if constexpr (NP > 0) {
-#pragma unroll
-    for (int j = 0; j < GT; ++j) lds_pair<P>(p + j * KC * CH, lane, a0[j], a1[j]);
-  }
-  Fr s[GT];
-  if constexpr (KC % 2 == 1) {
-#pragma unroll
-    for (int j = 0; j < GT; ++j) s[j] = lds_single<P>(p + j * KC * CH + (KC - 1) * CH, lane);
-  }
-#pragma unroll
-  for (int c = 0; c < NP; ++c) {
-    Fr b0[GT], b1[GT];
-    if (c + 1 < NP) {
-#pragma unroll
-      for (int j = 0; j < GT; ++j)
-        lds_pair<P>(p + j * KC * CH + (2 * c + 2) * CH, lane, b0[j], b1[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < GT; ++j)
-#pragma unroll
-      for (int n = 0; n < NT; ++n)
-        acc[j][n] = mma_pair<P>(acc[j][n], a0[j], a1[j], x[2 * c][n], x[2 * c + 1][n]);
-    if (c + 1 < NP) {
-#pragma unroll
-      for (int j = 0; j < GT; ++j) {
-        a0[j] = b0[j];
-        a1[j] = b1[j];
-      }
-    }
-  }
-  if constexpr (KC % 2 == 1) {
-#pragma unroll
-    for (int j = 0; j < GT; ++j)
-#pragma unroll
-      for (int n = 0; n < NT; ++n) acc[j][n] = mma_chunk<P>(acc[j][n], s[j], x[KC - 1][n]);
-  }
+// Software pipeline over the U units of one step: the LDS reads run D units
+// ahead of the matrix-core work that consumes them, in a ring of D + 1
+// fragment sets.  rd(u, slot) reads unit u; pre() runs once the first reads
+// are in flight (the VALU work that the step starts with); cs(u, slot)
+// issues unit u's MFMAs.
+template <int P, int U, int D, class Rd, class Pre, class Cs>
+__device__ __forceinline__ void lds_pipeline(Rd&& rd, Pre&& pre, Cs&& cs) {
+  constexpr int D0 = D < U ? D : U;
+  Unit<P> ring[D + 1];
+  static_for<D0>([&](auto ic) { rd(ic, ring[decltype(ic)::value]); });
+  pre();
+  static_for<U>([&](auto uc) {
+    constexpr int u = decltype(uc)::value;
+    if constexpr (u + D < U) rd(std::integral_constant<int, u + D>{}, ring[(u + D) % (D + 1)]);
+    cs(uc, ring[u % (D + 1)]);
+    // keeps the scheduler from sinking the reads back to their first use
+    __builtin_amdgcn_sched_barrier(0);
+  });
 }
 
 // Body force at integer node (x, y, z) in float32: the argument 2 pi k y / n
@@ -298,10 +264,12 @@ struct WideCfg {
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int SB = WL::max_step_bytes();
   static constexpr int NLD = (SB / 16 + THREADS - 1) / THREADS;  // 16-byte loads per thread
+  static constexpr int PD = P == P_F32 ? 2 : 3;  // LDS read distance of the step pipelines (units)
   // tile columns: g (Q), the bias input 1, zeros up to YC; y (Q, padded to 4)
   static constexpr int YC = (L::Q + 1 + 3) / 4 * 4;
   static constexpr int SX = YC + (L::Q + 3) / 4 * 4 + 4;  // row stride (floats)
   static constexpr int lds_bytes = 2 * SB + 4 * WL::nbias + 4 * WAVES * 64 * SX;
+  static_assert(NLD * THREADS * 16 >= SB, "one pass of stage loads covers a step");
 };
 
 template <class L, int P>
@@ -317,7 +285,11 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
   constexpr int Q = L::Q, NT = C::NT, NS = C::NS, SX = C::SX, SB = C::SB;
   constexpr int CH = WL::CHUNK;
 
-  __shared__ __attribute__((aligned(16))) unsigned char stage[2 * SB];
+  // step s is read from stage0 for even s, stage1 for odd s (NSTEP is even,
+  // so the assignment is the same in every sweep)
+  static_assert(WL::NSTEP % 2 == 0, "the stage buffers alternate by step parity");
+  __shared__ __attribute__((aligned(16))) unsigned char stage0[SB];
+  __shared__ __attribute__((aligned(16))) unsigned char stage1[SB];
   __shared__ __attribute__((aligned(16))) float bias[WL::nbias];
   __shared__ __attribute__((aligned(16))) float tiles[C::WAVES * 64 * SX];
 
@@ -334,29 +306,31 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
   const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * Q) * 4u;
   const rsrc_t src = make_rsrc(Ain, bytes), dst = make_rsrc(Aout, bytes);
 
-  // stage loads of step s (into registers), then their LDS commit
-  u4 sreg[C::NLD];
-  auto stage_issue = [&](int off, int nbytes) {
+  // loads of a step's packed weights straight into an LDS stage buffer
+  // (16 bytes per lane, a wavefront's 64 lanes fill 1 KB in lane order); they
+  // land while the matrix cores work on the other buffer, and the barrier at
+  // the end of the step waits for them
+  // (the lane part of the source offset is one register, tid * 16; the step
+  // and pass parts go to the scalar offset, kept opaque so that the compiler
+  // does not fold them into a vector register per load)
+  const int voff = tid * 16;
+  auto stage_issue = [&](unsigned char* dstbuf, int off, int nbytes) {
 #pragma unroll
     for (int j = 0; j < C::NLD; ++j) {
       const int i = tid + j * C::THREADS;
+      int so = off + j * C::THREADS * 16;
+      asm volatile("" : "+s"(so));
       if (i * 16 < nbytes)
-        sreg[j] = __builtin_bit_cast(u4, __builtin_amdgcn_raw_buffer_load_b128(wsrc, off + i * 16, 0, 0));
-    }
-  };
-  auto stage_commit = [&](unsigned char* dstbuf, int nbytes) {
-#pragma unroll
-    for (int j = 0; j < C::NLD; ++j) {
-      const int i = tid + j * C::THREADS;
-      if (i * 16 < nbytes) *reinterpret_cast<u4*>(dstbuf + i * 16) = sreg[j];
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            wsrc, (__attribute__((address_space(3))) void*)(dstbuf + (j * C::THREADS + wave * 64) * 16),
+            16, voff, so, 0, 0);
     }
   };
 
   // prologue: biases and step 0 into buffer 0
   for (int i = tid; i < WL::nbias; i += C::THREADS)
     bias[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(wsrc, WL::weight_bytes + 4 * i, 0, 0));
-  stage_issue(WL::step_offset(0), WL::step_bytes(0));
-  stage_commit(stage, WL::step_bytes(0));
+  stage_issue(stage0, WL::step_offset(0), WL::step_bytes(0));
   __syncthreads();
 
   ItemWalk cur, nxt;
@@ -368,7 +342,6 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
   }
 
   constexpr int YC = C::YC;
-  int parity = 0;  // LDS buffer holding the current step
   for (int k = 0; k < per; ++k) {
     const bool valid = it0 + k < nitems;
     const bool more = k + 1 < per && it0 + k + 1 < nitems;
@@ -390,16 +363,17 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
       static_for<WL::NSTEP>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
         constexpr int sn = (s + 1) % WL::NSTEP;
-        stage_issue(WL::step_offset(sn), WL::step_bytes(sn));
+        stage_issue(s % 2 == 0 ? stage1 : stage0, WL::step_offset(sn), WL::step_bytes(sn));
         if constexpr (s == 1 && sw == NS - 1) {
           if (more) {
             const Item tn = nxt.item(G, lane);
             gather_rows<L>(src, row_offsets(G, Q, tn.b, tn.y, tn.z), tn, gn);
           }
         }
-        const unsigned char* S = stage + parity * SB;
+        const unsigned char* S = s % 2 == 0 ? stage0 : stage1;
         if constexpr (s < WL::S1) {
-          // layer 1: h1 = leaky(W1 [g, 1]); input columns past YC are zero
+          // layer 1: h1 = leaky(W1 [g, 1]); input columns past YC are zero.
+          // Units: tile-major, chunk pairs then the odd chunk.
           if constexpr (s == 0) {
 #pragma unroll
             for (int n = 0; n < NT; ++n)
@@ -412,18 +386,30 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
                 x[c][n] = to_frag<P>(v);
               }
           }
-          static_for<WL::TP1>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            constexpr int tt = s * WL::TP1 + j;
-            if constexpr (tt < WL::T1) {
-              f4 acc[NT];
+          constexpr int NP = WL::K1 / 2, KU = NP + WL::K1 % 2, NTL = WL::l1_tiles(s);
+          f4 acc[NT];
+          lds_pipeline<P, NTL * KU, C::PD>(
+              [&](auto uc, Unit<P>& f) {
+                constexpr int u = decltype(uc)::value, j = u / KU, k = u % KU;
+                lds_unit<P, (k < NP)>(S + j * WL::K1 * CH + 2 * k * CH, lane, f);
+              },
+              [&] {},
+              [&](auto uc, const Unit<P>& f) {
+                constexpr int u = decltype(uc)::value, j = u / KU, k = u % KU;
+                constexpr int tt = s * WL::TP1 + j;
 #pragma unroll
-              for (int n = 0; n < NT; ++n) acc[n] = f4{0.f, 0.f, 0.f, 0.f};
-              tile_row<P, WL::K1, NT>(S + j * WL::K1 * CH, lane, acc, x);
+                for (int n = 0; n < NT; ++n) {
+                  const f4 a = k == 0 ? f4{0.f, 0.f, 0.f, 0.f} : acc[n];
+                  if constexpr (k < NP)
+                    acc[n] = mma_pair<P>(a, f.a0, f.a1, x[2 * k][n], x[2 * k + 1][n]);
+                  else
+                    acc[n] = mma_chunk<P>(a, f.a0, x[WL::K1 - 1][n]);
+                }
+                if constexpr (k == KU - 1) {
 #pragma unroll
-              for (int n = 0; n < NT; ++n) h1[tt][n] = to_frag<P>(leaky4(acc[n]));
-            }
-          });
+                  for (int n = 0; n < NT; ++n) h1[tt][n] = to_frag<P>(leaky4(acc[n]));
+                }
+              });
           if constexpr (s == WL::S1 - 1) {
 #pragma unroll
             for (int t3 = 0; t3 < WL::T3; ++t3) {
@@ -433,63 +419,104 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
             }
           }
         } else if constexpr (s < WL::S1 + WL::NG) {
-          // layer-2 tiles of group g, then their share of layer 3
+          // layer-2 tiles of group g, then their share of layer 3.  Units:
+          // layer-2 chunk pairs (pair-major, tile-minor, so consecutive MFMAs
+          // feed different accumulators), the odd layer-2 chunk of each
+          // tile, then one unit per layer-3 tile; the layer-3 reads are in
+          // flight while the last layer-2 MFMAs and the activation run.
           constexpr int g = s - WL::S1;
           constexpr int GT = WL::group_tiles(g);
-          F h2[WL::RG][NT];
-          {
-            f4 acc[GT][NT];
-#pragma unroll
-            for (int j = 0; j < GT; ++j) {
-              const f4 b = *reinterpret_cast<const f4*>(bias + WL::fb2 + 16 * (g * WL::RG + j) + 4 * lg);
-#pragma unroll
-              for (int n = 0; n < NT; ++n) acc[j][n] = b;
-            }
-            tiles_row<P, WL::K2, NT, GT>(S, lane, acc, h1);
-#pragma unroll
-            for (int j = 0; j < GT; ++j)
-#pragma unroll
-              for (int n = 0; n < NT; ++n) h2[j][n] = to_frag<P>(leaky4(acc[j][n]));
-          }
+          constexpr int NP = WL::K2 / 2, KU = NP + WL::K2 % 2, U2 = KU * GT;
           const unsigned char* S3 = S + GT * WL::K2 * CH;
+          f4 acc[GT][NT];
+          F h2[WL::RG][NT];
 #pragma unroll
-          for (int t3 = 0; t3 < WL::T3; ++t3) {
-            if constexpr (GT == 2) {
-              F a0, a1;
-              lds_pair<P>(S3 + t3 * 2 * CH, lane, a0, a1);
+          for (int j = 0; j < GT; ++j) {
+            const f4 b = *reinterpret_cast<const f4*>(bias + WL::fb2 + 16 * (g * WL::RG + j) + 4 * lg);
 #pragma unroll
-              for (int n = 0; n < NT; ++n)
-                acc3[t3][n] = mma_pair<P>(acc3[t3][n], a0, a1, h2[0][n], h2[WL::RG - 1][n]);
-            } else {
-              const F a = lds_single<P>(S3 + t3 * CH, lane);
-#pragma unroll
-              for (int n = 0; n < NT; ++n) acc3[t3][n] = mma_chunk<P>(acc3[t3][n], a, h2[0][n]);
-            }
+            for (int n = 0; n < NT; ++n) acc[j][n] = b;
           }
+          lds_pipeline<P, U2 + WL::T3, C::PD>(
+              [&](auto uc, Unit<P>& f) {
+                constexpr int u = decltype(uc)::value;
+                if constexpr (u < U2) {
+                  constexpr int k = u / GT, j = u % GT;
+                  lds_unit<P, (k < NP)>(S + j * WL::K2 * CH + 2 * k * CH, lane, f);
+                } else {
+                  lds_unit<P, (GT == 2)>(S3 + (u - U2) * GT * CH, lane, f);
+                }
+              },
+              [&] {},
+              [&](auto uc, const Unit<P>& f) {
+                constexpr int u = decltype(uc)::value;
+                if constexpr (u < U2) {
+                  constexpr int k = u / GT, j = u % GT;
+#pragma unroll
+                  for (int n = 0; n < NT; ++n) {
+                    if constexpr (k < NP)
+                      acc[j][n] = mma_pair<P>(acc[j][n], f.a0, f.a1, h1[2 * k][n], h1[2 * k + 1][n]);
+                    else
+                      acc[j][n] = mma_chunk<P>(acc[j][n], f.a0, h1[WL::K2 - 1][n]);
+                  }
+                  if constexpr (u == U2 - 1) {
+#pragma unroll
+                    for (int jj = 0; jj < GT; ++jj)
+#pragma unroll
+                      for (int n = 0; n < NT; ++n) h2[jj][n] = to_frag<P>(leaky4(acc[jj][n]));
+                  }
+                } else {
+                  constexpr int t3 = u - U2;
+#pragma unroll
+                  for (int n = 0; n < NT; ++n) {
+                    if constexpr (GT == 2)
+                      acc3[t3][n] = mma_pair<P>(acc3[t3][n], f.a0, f.a1, h2[0][n], h2[WL::RG - 1][n]);
+                    else
+                      acc3[t3][n] = mma_chunk<P>(acc3[t3][n], f.a0, h2[0][n]);
+                  }
+                }
+              });
         } else {
-          // layer 4: y = W4 leaky(acc3) + b4, rows < Q written to the tile
+          // layer 4: y = W4 leaky(acc3) + b4, rows < Q written to the tile.
+          // Units: chunk-major, tile-minor.
+          constexpr int NP = WL::K4 / 2, KU = NP + WL::K4 % 2;
           F h3[WL::T3][NT];
+          f4 acc[WL::T4][NT];
+          lds_pipeline<P, KU * WL::T4, C::PD>(
+              [&](auto uc, Unit<P>& f) {
+                constexpr int u = decltype(uc)::value, k = u / WL::T4, t4 = u % WL::T4;
+                lds_unit<P, (k < NP)>(S + t4 * WL::K4 * CH + 2 * k * CH, lane, f);
+              },
+              [&] {
 #pragma unroll
-          for (int t3 = 0; t3 < WL::T3; ++t3)
+                for (int t3 = 0; t3 < WL::T3; ++t3)
 #pragma unroll
-            for (int n = 0; n < NT; ++n) h3[t3][n] = to_frag<P>(leaky4(acc3[t3][n]));
+                  for (int n = 0; n < NT; ++n) h3[t3][n] = to_frag<P>(leaky4(acc3[t3][n]));
 #pragma unroll
-          for (int t4 = 0; t4 < WL::T4; ++t4) {
-            f4 acc[NT];
-            const f4 b = *reinterpret_cast<const f4*>(bias + WL::fb4 + 16 * t4 + 4 * lg);
+                for (int t4 = 0; t4 < WL::T4; ++t4) {
+                  const f4 b = *reinterpret_cast<const f4*>(bias + WL::fb4 + 16 * t4 + 4 * lg);
 #pragma unroll
-            for (int n = 0; n < NT; ++n) acc[n] = b;
-            tile_row<P, WL::K4, NT>(S + t4 * WL::K4 * CH, lane, acc, h3);
-            const int row = 16 * t4 + 4 * lg;
-            if (row < Q) {
+                  for (int n = 0; n < NT; ++n) acc[t4][n] = b;
+                }
+              },
+              [&](auto uc, const Unit<P>& f) {
+                constexpr int u = decltype(uc)::value, k = u / WL::T4, t4 = u % WL::T4;
 #pragma unroll
-              for (int n = 0; n < NT; ++n)
-                *reinterpret_cast<f4*>(T + (row0 + 16 * n + li) * SX + YC + row) = acc[n];
-            }
-          }
+                for (int n = 0; n < NT; ++n) {
+                  if constexpr (k < NP)
+                    acc[t4][n] = mma_pair<P>(acc[t4][n], f.a0, f.a1, h3[2 * k][n], h3[2 * k + 1][n]);
+                  else
+                    acc[t4][n] = mma_chunk<P>(acc[t4][n], f.a0, h3[WL::K4 - 1][n]);
+                }
+                if constexpr (k == KU - 1) {
+                  const int row = 16 * t4 + 4 * lg;
+                  if (row < Q) {
+#pragma unroll
+                    for (int n = 0; n < NT; ++n)
+                      *reinterpret_cast<f4*>(T + (row0 + 16 * n + li) * SX + YC + row) = acc[t4][n];
+                  }
+                }
+              });
         }
-        stage_commit(stage + (parity ^ 1) * SB, WL::step_bytes(sn));
-        parity ^= 1;
         __syncthreads();
       });
     });

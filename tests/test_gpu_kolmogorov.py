@@ -2,7 +2,7 @@
 forcing, tau 0.51, 9->64->64->9 tanh): the float32 and bf16 networks
 against the FP64 oracle on the velocity moments and the energy spectrum, on
 a 128^2 field for 100 steps, and the bf16 run against the float32 run on the
-1024^2 field for 2000 steps (spectra in float64 on the host)."""
+1024^2 field for 10,000 steps (spectra in float64 on the host)."""
 import numpy as np
 import pytest
 
@@ -81,7 +81,7 @@ def test_kolmogorov_128_against_oracle(lbm):
 
 
 def test_kolmogorov_1024_bf16_vs_fp32(lbm):
-    n, steps = 1024, 2000
+    n, steps = 1024, 10000
     ocfg = kolmogorov_cfg(n)
     g0 = initial_state(ocfg)
     theta = torch.from_numpy(inputs.glorot_params(9, 64, seed=1)).cuda()
