@@ -14,15 +14,19 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm_hip.so")
+# matrix-core results in VGPRs, read by the activation without
+# accumulator-register moves
+VGPR_FORM = ("-mllvm", "-amdgpu-mfma-vgpr-form")
 # (source, extra flags): the wide-network kernels use the max-ILP instruction
 # scheduler, which keeps their LDS weight reads ahead of the matrix-core work,
 SOURCES = [
-    (os.path.join(CSRC, "lbm_api.hip"), ()),
+    (os.path.join(CSRC, "lbm_api.hip"), VGPR_FORM),
     # and IEEE mode off (LeakyReLU's max then needs no NaN-quieting
     # canonicalisation; the wide step has no NaN tests)
-    (os.path.join(CSRC, "wide.hip"), ("-mllvm", "-amdgpu-sched-strategy=max-ilp",
-                                      "-mno-amdgpu-ieee", "-fno-honor-nans")),
-    (os.path.join(CSRC, "wide_bwd.hip"), ()),
+    (os.path.join(CSRC, "wide.hip"), VGPR_FORM + ("-mllvm", "-amdgpu-sched-strategy=max-ilp",
+                                                  "-mno-amdgpu-ieee", "-fno-honor-nans")),
+    (os.path.join(CSRC, "wide_bwd.hip"), VGPR_FORM),
+    (os.path.join(CSRC, "nlbm_bwd.hip"), VGPR_FORM),
 ]
 
 
@@ -38,9 +42,6 @@ def compile_command(src: str, obj: str, extra=()):
         hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-c",
         # no packed FP32 instructions anywhere in the device code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        # matrix-core results in VGPRs, read by the activation without
-        # accumulator-register moves
-        "-mllvm", "-amdgpu-mfma-vgpr-form",
         "-Wno-unused-command-line-argument",
         "-I", os.path.join(ROOT, "include"), "-I", CSRC,
         *extra, src, "-o", obj,

@@ -137,6 +137,12 @@ __global__ __launch_bounds__(256) void bgk_backward_kernel(const float* __restri
 // ---------------------------------------------------------------------------
 constexpr unsigned bwd_blocks(int ncu) { return (unsigned)ncu; }
 
+// 16-node groups differentiated together (two wherever their transpose
+// tiles fit in the LDS; the D3Q19 instances fall back to one)
+#ifndef LBM_BWD_GROUPS
+#define LBM_BWD_GROUPS 2
+#endif
+
 template <class L, int H, int P>
 struct BwdLayout {
   using S = Shape<L::Q, H>;
@@ -150,25 +156,16 @@ struct BwdLayout {
   // two feature-major transpose tiles: h2 then d2 in the first, h1 then d1
   // in the second (a wave's LDS accesses complete in issue order, so a tile
   // can be rewritten once its previous contents have been read)
-  static constexpr int per_wave = 64 * SX + 64 * SD + 2 * H * ST;
+  // 16-node groups a wavefront differentiates at once (independent chains
+  // the scheduler can interleave), each with its own transpose tiles
+  static constexpr int wave_floats(int ngp) { return 64 * SX + 64 * SD + ngp * 2 * H * ST; }
+  static constexpr int frag_bytes = (P == P_F32 ? 16 : 8) * 64;
+  static constexpr bool fits(int ngp) {
+    return 4 * 4 * wave_floats(ngp) + NF * frag_bytes <= 160 * 1024;
+  }
+  static constexpr int NGP = fits(LBM_BWD_GROUPS) ? LBM_BWD_GROUPS : 1;
+  static constexpr int per_wave = wave_floats(NGP);
 };
-
-// Transpose of NB 16x16 chunks in D layout (lane l: rows 4g + r of column i)
-// into the "node as contraction" operand layout (lane l: row i, columns
-// 4g + r), through a feature-major scratch tile T of stride ST: all writes,
-// one wave-level LDS ordering point, all reads.
-template <int P, int ST, int NB>
-__device__ inline void transpose_chunks(float* T, const f4 (&v)[NB], typename Frag<P>::T (&out)[NB],
-                                        int lg, int li) {
-#pragma unroll
-  for (int blk = 0; blk < NB; ++blk)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) T[(16 * blk + 4 * lg + r) * ST + li] = v[blk][r];
-  wave_lds_sync();
-#pragma unroll
-  for (int blk = 0; blk < NB; ++blk)
-    out[blk] = to_frag<P>(*reinterpret_cast<const f4*>(T + (16 * blk + li) * ST + 4 * lg));
-}
 
 template <class L, int H, int P>
 __global__ __launch_bounds__(256) void nlbm_backward_kernel(
@@ -298,98 +295,174 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
     }
     wave_lds_sync();
 
-#pragma unroll 1
-    for (int jg = 0; jg < 4; ++jg) {
-      const int nrow = 16 * jg + li;
+    // NG consecutive 16-node groups at a time, stage by stage, so that the
+    // scheduler has NG independent chains between the LDS ordering points;
+    // the weight gradients contract over all 16 NG nodes at once.
+    constexpr int NG = BL::NGP;
+    auto groups = [&](const int jg0) {
+      Fr xin[NG][S::KX], h1[NG][S::HB], h2[NG][S::HB], dyf[NG][S::QB], dyT[NG][S::QB];
+      f4 t1[NG][S::HB], t2[NG][S::HB], d2[NG][S::HB], d1[NG][S::HB];
+      Fr d2f[NG][S::HB], d1f[NG][S::HB];
       // forward recompute
-      Fr xin[S::KX];
 #pragma unroll
-      for (int c = 0; c < S::KX; ++c)
-        xin[c] = to_frag<P>(*reinterpret_cast<const f4*>(X + nrow * BL::SX + 16 * c + 4 * lg));
-      f4 t1[S::HB], t2[S::HB];
-      Fr h1[S::HB], h2[S::HB];
+      for (int e = 0; e < NG; ++e)
 #pragma unroll
-      for (int ob = 0; ob < S::HB; ++ob) {
-        t1[ob] = tanh4<P>(mma_row<P, S::KX>(f4{0.f, 0.f, 0.f, 0.f}, W.w1[ob], xin));
-        h1[ob] = to_frag<P>(t1[ob]);
-      }
+        for (int c = 0; c < S::KX; ++c)
+          xin[e][c] = to_frag<P>(*reinterpret_cast<const f4*>(X + (16 * (jg0 + e) + li) * BL::SX + 16 * c + 4 * lg));
 #pragma unroll
-      for (int ob = 0; ob < S::HB; ++ob) {
-        t2[ob] = tanh4<P>(mma_row<P, S::HB>(W.b2[ob], W.w2[ob], h1));
-        h2[ob] = to_frag<P>(t2[ob]);
-      }
+      for (int ob = 0; ob < S::HB; ++ob)
+#pragma unroll
+        for (int e = 0; e < NG; ++e) {
+          t1[e][ob] = tanh4<P>(mma_row<P, S::KX>(f4{0.f, 0.f, 0.f, 0.f}, W.w1[ob], xin[e]));
+          h1[e][ob] = to_frag<P>(t1[e][ob]);
+        }
+#pragma unroll
+      for (int ob = 0; ob < S::HB; ++ob)
+#pragma unroll
+        for (int e = 0; e < NG; ++e) {
+          t2[e][ob] = tanh4<P>(mma_row<P, S::HB>(W.b2[ob], W.w2[ob], h1[e]));
+          h2[e][ob] = to_frag<P>(t2[e][ob]);
+        }
       // dy in both operand layouts
-      Fr dyf[S::QB], dyT[S::QB];
 #pragma unroll
-      for (int qc = 0; qc < S::QB; ++qc) {
-        dyf[qc] = to_frag<P>(*reinterpret_cast<const f4*>(D + nrow * BL::SD + 16 * qc + 4 * lg));
-        f4 v;
+      for (int e = 0; e < NG; ++e)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = D[(16 * jg + 4 * lg + r) * BL::SD + 16 * qc + li];
-        dyT[qc] = to_frag<P>(v);
-      }
+        for (int qc = 0; qc < S::QB; ++qc) {
+          const int jg = jg0 + e;
+          dyf[e][qc] = to_frag<P>(*reinterpret_cast<const f4*>(D + (16 * jg + li) * BL::SD + 16 * qc + 4 * lg));
+          f4 v;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[r] = D[(16 * jg + 4 * lg + r) * BL::SD + 16 * qc + li];
+          dyT[e][qc] = to_frag<P>(v);
+        }
       // d2 = (W3^T dy) (1 - t2^2)
-      f4 d2[S::HB];
-      Fr d2f[S::HB];
 #pragma unroll
-      for (int ob = 0; ob < S::HB; ++ob) {
-        f4 a = mma_row_lds<P, S::QB>(f4{0.f, 0.f, 0.f, 0.f}, W3T + ob * S::QB * 64 + lane, dyf);
-        d2[ob] = a * (1.f - t2[ob] * t2[ob]);
-        db2[ob] += d2[ob];
-        d2f[ob] = to_frag<P>(d2[ob]);
-      }
+      for (int ob = 0; ob < S::HB; ++ob)
+#pragma unroll
+        for (int e = 0; e < NG; ++e) {
+          f4 a = mma_row_lds<P, S::QB>(f4{0.f, 0.f, 0.f, 0.f}, W3T + ob * S::QB * 64 + lane, dyf[e]);
+          d2[e][ob] = a * (1.f - t2[e][ob] * t2[e][ob]);
+          db2[ob] += d2[e][ob];
+          d2f[e][ob] = to_frag<P>(d2[e][ob]);
+        }
       // d1 = (W2^T d2) (1 - t1^2)
-      f4 d1[S::HB];
-      Fr d1f[S::HB];
 #pragma unroll
-      for (int ob = 0; ob < S::HB; ++ob) {
-        f4 a = mma_row_lds<P, S::HB>(f4{0.f, 0.f, 0.f, 0.f}, W2T + ob * S::HB * 64 + lane, d2f);
-        if constexpr (sc != 1.f) a = a * (1.f / sc);
-        d1[ob] = a * (1.f - t1[ob] * t1[ob]);
-        d1f[ob] = to_frag<P>(d1[ob]);
-      }
-      // weight gradients, contraction over the 16 nodes of the group
+      for (int ob = 0; ob < S::HB; ++ob)
+#pragma unroll
+        for (int e = 0; e < NG; ++e) {
+          f4 a = mma_row_lds<P, S::HB>(f4{0.f, 0.f, 0.f, 0.f}, W2T + ob * S::HB * 64 + lane, d2f[e]);
+          if constexpr (sc != 1.f) a = a * (1.f / sc);
+          d1[e][ob] = a * (1.f - t1[e][ob] * t1[e][ob]);
+          d1f[e][ob] = to_frag<P>(d1[e][ob]);
+        }
+      // weight gradients, contraction over the 16 NG nodes of the groups;
+      // group e's transpose tiles are T_e and T_e + H ST
+      auto Te = [&](int e, int k) { return T + (2 * e + k) * H * BL::ST; };
+      auto wgrad = [&](f4& acc, const Fr (&a)[NG], const Fr (&b)[NG]) {
+        if constexpr (NG == 2)
+          acc = mma_pair<P>(acc, a[0], a[1], b[0], b[1]);
+        else
+          acc = mma_chunk<P>(acc, a[0], b[0]);
+      };
       {
-        Fr h2T[S::HB];
-        transpose_chunks<P, BL::ST, S::HB>(T, t2, h2T, lg, li);
+        Fr h2T[S::HB][NG], dyTT[S::QB][NG];
+#pragma unroll
+        for (int e = 0; e < NG; ++e) {
+#pragma unroll
+          for (int blk = 0; blk < S::HB; ++blk)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Te(e, 0)[(16 * blk + 4 * lg + r) * BL::ST + li] = t2[e][blk][r];
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int e = 0; e < NG; ++e) {
+#pragma unroll
+          for (int blk = 0; blk < S::HB; ++blk)
+            h2T[blk][e] = to_frag<P>(*reinterpret_cast<const f4*>(Te(e, 0) + (16 * blk + li) * BL::ST + 4 * lg));
+#pragma unroll
+          for (int qc = 0; qc < S::QB; ++qc) dyTT[qc][e] = dyT[e][qc];
+        }
 #pragma unroll
         for (int qc = 0; qc < S::QB; ++qc)
 #pragma unroll
-          for (int ib = 0; ib < S::HB; ++ib) dW3[qc][ib] = mma_chunk<P>(dW3[qc][ib], dyT[qc], h2T[ib]);
+          for (int ib = 0; ib < S::HB; ++ib) wgrad(dW3[qc][ib], dyTT[qc], h2T[ib]);
       }
       {
-        Fr h1T[S::HB], d2T[S::HB];
-        transpose_chunks<P, BL::ST, S::HB>(T + H * BL::ST, t1, h1T, lg, li);
-        transpose_chunks<P, BL::ST, S::HB>(T, d2, d2T, lg, li);
+        Fr h1T[S::HB][NG], d2T[S::HB][NG];
+#pragma unroll
+        for (int e = 0; e < NG; ++e)
+#pragma unroll
+          for (int blk = 0; blk < S::HB; ++blk)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Te(e, 1)[(16 * blk + 4 * lg + r) * BL::ST + li] = t1[e][blk][r];
+        wave_lds_sync();
+#pragma unroll
+        for (int e = 0; e < NG; ++e)
+#pragma unroll
+          for (int blk = 0; blk < S::HB; ++blk)
+            h1T[blk][e] = to_frag<P>(*reinterpret_cast<const f4*>(Te(e, 1) + (16 * blk + li) * BL::ST + 4 * lg));
+        // the h2 tile has been read: reuse it for d2
+        wave_lds_sync();
+#pragma unroll
+        for (int e = 0; e < NG; ++e)
+#pragma unroll
+          for (int blk = 0; blk < S::HB; ++blk)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Te(e, 0)[(16 * blk + 4 * lg + r) * BL::ST + li] = d2[e][blk][r];
+        wave_lds_sync();
+#pragma unroll
+        for (int e = 0; e < NG; ++e)
+#pragma unroll
+          for (int blk = 0; blk < S::HB; ++blk)
+            d2T[blk][e] = to_frag<P>(*reinterpret_cast<const f4*>(Te(e, 0) + (16 * blk + li) * BL::ST + 4 * lg));
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob)
 #pragma unroll
-          for (int ib = 0; ib < S::HB; ++ib) dW2[ob][ib] = mma_chunk<P>(dW2[ob][ib], d2T[ob], h1T[ib]);
+          for (int ib = 0; ib < S::HB; ++ib) wgrad(dW2[ob][ib], d2T[ob], h1T[ib]);
       }
       {
-        Fr d1T[S::HB], x0T[S::KX];
-        transpose_chunks<P, BL::ST, S::HB>(T + H * BL::ST, d1, d1T, lg, li);
+        Fr d1T[S::HB][NG], x0T[S::KX][NG];
+        wave_lds_sync();
 #pragma unroll
-        for (int c = 0; c < S::KX; ++c) {
-          f4 v;
+        for (int e = 0; e < NG; ++e)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) v[r] = X[(16 * jg + 4 * lg + r) * BL::SX + 16 * c + li];
-          x0T[c] = to_frag<P>(v);
+          for (int blk = 0; blk < S::HB; ++blk)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Te(e, 1)[(16 * blk + 4 * lg + r) * BL::ST + li] = d1[e][blk][r];
+        wave_lds_sync();
+#pragma unroll
+        for (int e = 0; e < NG; ++e) {
+#pragma unroll
+          for (int blk = 0; blk < S::HB; ++blk)
+            d1T[blk][e] = to_frag<P>(*reinterpret_cast<const f4*>(Te(e, 1) + (16 * blk + li) * BL::ST + 4 * lg));
+#pragma unroll
+          for (int c = 0; c < S::KX; ++c) {
+            f4 v;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = X[(16 * (jg0 + e) + 4 * lg + r) * BL::SX + 16 * c + li];
+            x0T[c][e] = to_frag<P>(v);
+          }
         }
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob)
 #pragma unroll
-          for (int c = 0; c < S::KX; ++c) dW1[ob][c] = mma_chunk<P>(dW1[ob][c], d1T[ob], x0T[c]);
+          for (int c = 0; c < S::KX; ++c) wgrad(dW1[ob][c], d1T[ob], x0T[c]);
       }
-      // dx = W1^T d1, over the input rows of this group (overwrites the
-      // group's own dy rows, which are no longer read)
+      // dx = W1^T d1, over the input rows of these groups (overwrites the
+      // groups' own dy rows, which are no longer read)
 #pragma unroll
-      for (int c = 0; c < S::KX; ++c) {
-        f4 a = mma_row_lds<P, S::HB>(f4{0.f, 0.f, 0.f, 0.f}, W1T + c * S::HB * 64 + lane, d1f);
-        if constexpr (sc != 1.f) a = a * (1.f / sc);
-        *reinterpret_cast<f4*>(D + nrow * BL::SD + 16 * c + 4 * lg) = a;
-      }
-    }
+      for (int c = 0; c < S::KX; ++c)
+#pragma unroll
+        for (int e = 0; e < NG; ++e) {
+          f4 a = mma_row_lds<P, S::HB>(f4{0.f, 0.f, 0.f, 0.f}, W1T + c * S::HB * 64 + lane, d1f[e]);
+          if constexpr (sc != 1.f) a = a * (1.f / sc);
+          *reinterpret_cast<f4*>(D + (16 * (jg0 + e) + li) * BL::SD + 16 * c + 4 * lg) = a;
+        }
+      // the transpose tiles are rewritten by the next groups
+      wave_lds_sync();
+    };
+#pragma unroll 1
+    for (int jp = 0; jp < 4; jp += NG) groups(jp);
     wave_lds_sync();
 #pragma unroll
     for (int q = 0; q < Q; ++q) lam[q] += D[lane * BL::SD + q];
@@ -482,5 +555,11 @@ static __global__ __launch_bounds__(256) void grad_reduce_kernel(const float* __
   if (sl == 0 && p < np)
     dtheta[p] += (float)(((red[0][pl] + red[1][pl]) + red[2][pl]) + red[3][pl]);
 }
+
+// Launch of nlbm_backward_kernel<L, H, P>, defined in nlbm_bwd.hip.
+hipError_t nlbm_bwd_launch(bool d3q19, int hidden, int prec, unsigned blocks, hipStream_t s,
+                           const float* A, const float* theta, const float* lam1, float* lam0,
+                           float* part, Grid G, Force Fc, float rho0, float omega, float knn,
+                           int nitems, int nxc);
 
 }  // namespace lbm

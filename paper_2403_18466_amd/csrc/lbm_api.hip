@@ -414,10 +414,11 @@ lbm_status launch_bwd(lbm_ctx* ctx, const float* A, const float* theta, const fl
   const int nparam = (int)param_count(c);
   float* part = static_cast<float*>(ws);
   const unsigned blocks = bwd_blocks(ctx->ncu);
-  hipLaunchKernelGGL((nlbm_backward_kernel<L, H, P>), dim3(blocks), dim3(256), 0, s, A, theta,
-                     lam1, lam0, part, G, force_of(c), (float)c.rho0, (float)(1.0 / c.tau),
-                     (float)(c.out_scale / c.tau), (int)nitems, nxc);
-  LBM_LAUNCHED("nlbm_backward_kernel");
+  hipError_t e = nlbm_bwd_launch(L::Q == 19, H, P, blocks, s, A, theta, lam1, lam0, part, G,
+                                 force_of(c), (float)c.rho0, (float)(1.0 / c.tau),
+                                 (float)(c.out_scale / c.tau), (int)nitems, nxc);
+  if (e != hipSuccess)
+    return fail(LBM_ERR_HIP, std::string("launch of nlbm_backward_kernel: ") + hipGetErrorString(e));
   hipLaunchKernelGGL(grad_reduce_kernel, dim3(blocks_for(nparam, 64)), dim3(256), 0, s, part,
                      (int)blocks, nparam, dtheta);
   LBM_LAUNCHED("grad_reduce_kernel");
