@@ -57,7 +57,10 @@ WsLayout ws_layout(long long nodes, size_t es) {
 template <int P, int EPI>
 hipError_t gemm(hipStream_t s, const GemmArgs& a, long long M, int N, int splits) {
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)splits);
-  hipLaunchKernelGGL((gemm_nt_kernel<P, EPI>), grid, dim3(256), 0, s, a);
+  if constexpr (P == P_F32)
+    hipLaunchKernelGGL((gemm_nt_kernel<P, EPI>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((gemm_nt16_kernel<P, EPI>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -210,6 +210,42 @@ struct GemmArgs {
   long long slab;  // EPI_PARTIAL: elements between consecutive K-range slabs
 };
 
+// Epilogue of a wavefront's 32 x 32 block at (ib, jb); D layout: lane
+// (lg, li) holds rows 4 lg + r, column li of each 16 x 16 tile.
+template <int P, int EPI>
+__device__ inline void gemm_epilogue(const GemmArgs& a, const f4 (&acc)[2][2], int ib, int jb,
+                                     int lg, int li) {
+  using T = typename OpT<P>::T;
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int j = jb + 16 * t + li;
+      if (j >= a.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = ib + 16 * s + 4 * lg + r;
+        if (i >= a.M) continue;
+        float v = acc[s][t][r];
+        if constexpr (EPI == EPI_LEAKY) {
+          v += a.bias[j];
+          v = v > 0.f ? v : kLeakySlope * v;
+        } else if constexpr (EPI == EPI_MASK) {
+          const float m = (float)static_cast<const T*>(a.mask)[(long long)i * a.ldc + j];
+          v = m > 0.f ? v : kLeakySlope * v;
+        }
+        if constexpr (EPI == EPI_LEAKY || EPI == EPI_MASK) {
+          static_cast<T*>(a.C)[(long long)i * a.ldc + j] = to_op<P>(v);
+          if (a.Ct) static_cast<T*>(a.Ct)[(long long)j * a.ldct + i] = to_op<P>(v);
+        } else if constexpr (EPI == EPI_F32) {
+          static_cast<float*>(a.C)[(long long)i * a.ldc + j] = v;
+        } else {
+          static_cast<float*>(a.C)[(long long)blockIdx.z * a.slab + (long long)i * a.ldc + j] = v;
+        }
+      }
+    }
+}
+
 template <int P, int EPI>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs a) {
   using T = typename OpT<P>::T;
@@ -264,35 +300,84 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs a) {
     }
     __syncthreads();
   }
-  // D layout: lane (lg, li) holds rows 4 lg + r, column li of each subtile
+  gemm_epilogue<P, EPI>(a, acc, i0 + wi, j0 + wj, lg, li);
+}
+
+// The same product for 16-bit operands, 64 x 64 tiles of four wavefronts
+// (32 x 32 each, 2 x 2 MFMA tiles), K steps of 32:
+//  * every thread loads 8 consecutive k of one row of A and of B per step
+//    (16-byte loads; M, N and K are multiples of 8 here, so a chunk is
+//    either wholly inside or wholly outside the operand);
+//  * the next step's chunks are in registers while the current step's
+//    MFMAs run, then go to the other of two LDS buffers (one barrier per
+//    step);
+//  * a lane's operand of one 16 x 16 x 32 MFMA is one 16-byte LDS read: row
+//    li of the tile, k = 8 lg .. 8 lg + 7, for A and for B alike, so the
+//    contraction pairs the same k on both sides.
+template <int P, int EPI>
+__global__ __launch_bounds__(256) void gemm_nt16_kernel(GemmArgs a) {
+  static_assert(P != P_F32, "16-bit operands");
+  using T = typename OpT<P>::T;
+  constexpr int SK = 32 + 8;  // LDS row stride (elements): 80 bytes
+  __shared__ __attribute__((aligned(16))) T As[2][64 * SK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][64 * SK];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lg = lane >> 4, li = lane & 15;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const long long k_begin = (long long)blockIdx.z * a.kc;
+  long long k_end = k_begin + a.kc;
+  if (k_end > a.K) k_end = a.K;
+  const T* A = static_cast<const T*>(a.A);
+  const T* B = static_cast<const T*>(a.B);
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  // staging: thread -> row tid / 4 of each tile, k (tid % 4) * 8 .. + 7
+  const int sr = tid >> 2, sk = (tid & 3) * 8;
+  const bool rowA = i0 + sr < a.M, rowB = j0 + sr < a.N;
+  const T* pa = A + (long long)(rowA ? i0 + sr : 0) * a.lda + sk;
+  const T* pb = B + (long long)(rowB ? j0 + sr : 0) * a.ldb + sk;
+  auto fetch = [&](long long k0, u4& va, u4& vb) {
+    const bool in = k0 + sk < k_end;
+    va = (rowA && in) ? *reinterpret_cast<const u4*>(pa + k0) : u4{0u, 0u, 0u, 0u};
+    vb = (rowB && in) ? *reinterpret_cast<const u4*>(pb + k0) : u4{0u, 0u, 0u, 0u};
+  };
+  f4 acc[2][2];
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int j = j0 + wj + 16 * t + li;
-      if (j >= a.N) continue;
+    for (int t = 0; t < 2; ++t) acc[s][t] = f4{0.f, 0.f, 0.f, 0.f};
+  u4 va, vb;
+  fetch(k_begin, va, vb);
+  *reinterpret_cast<u4*>(&As[0][sr * SK + sk]) = va;
+  *reinterpret_cast<u4*>(&Bs[0][sr * SK + sk]) = vb;
+  __syncthreads();
+  int buf = 0;
+  for (long long k0 = k_begin; k0 < k_end; k0 += 32) {
+    const bool more = k0 + 32 < k_end;
+    if (more) fetch(k0 + 32, va, vb);
+    u4 af[2], bf[2];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wi + 16 * s + 4 * lg + r;
-        if (i >= a.M) continue;
-        float v = acc[s][t][r];
-        if constexpr (EPI == EPI_LEAKY) {
-          v += a.bias[j];
-          v = v > 0.f ? v : kLeakySlope * v;
-        } else if constexpr (EPI == EPI_MASK) {
-          const float m = (float)static_cast<const T*>(a.mask)[(long long)i * a.ldc + j];
-          v = m > 0.f ? v : kLeakySlope * v;
-        }
-        if constexpr (EPI == EPI_LEAKY || EPI == EPI_MASK) {
-          static_cast<T*>(a.C)[(long long)i * a.ldc + j] = to_op<P>(v);
-          if (a.Ct) static_cast<T*>(a.Ct)[(long long)j * a.ldct + i] = to_op<P>(v);
-        } else if constexpr (EPI == EPI_F32) {
-          static_cast<float*>(a.C)[(long long)i * a.ldc + j] = v;
-        } else {
-          static_cast<float*>(a.C)[(long long)blockIdx.z * a.slab + (long long)i * a.ldc + j] = v;
-        }
-      }
+    for (int s = 0; s < 2; ++s) {
+      af[s] = *reinterpret_cast<const u4*>(&As[buf][(wi + 16 * s + li) * SK + 8 * lg]);
+      bf[s] = *reinterpret_cast<const u4*>(&Bs[buf][(wj + 16 * s + li) * SK + 8 * lg]);
     }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        if constexpr (P == P_BF16)
+          acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(b8, af[s]), __builtin_bit_cast(b8, bf[t]), acc[s][t], 0, 0, 0);
+        else
+          acc[s][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+              __builtin_bit_cast(h8, af[s]), __builtin_bit_cast(h8, bf[t]), acc[s][t], 0, 0, 0);
+      }
+    if (more) {
+      *reinterpret_cast<u4*>(&As[buf ^ 1][sr * SK + sk]) = va;
+      *reinterpret_cast<u4*>(&Bs[buf ^ 1][sr * SK + sk]) = vb;
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  gemm_epilogue<P, EPI>(a, acc, i0 + wi, j0 + wj, lg, li);
 }
 
 // dtheta[p] += sum over the nsplit slabs (fixed order) of the padded weight
