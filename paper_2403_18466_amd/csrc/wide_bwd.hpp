@@ -377,7 +377,56 @@ __global__ __launch_bounds__(256) void gemm_nt16_kernel(GemmArgs a) {
     __syncthreads();
     buf ^= 1;
   }
-  gemm_epilogue<P, EPI>(a, acc, i0 + wi, j0 + wj, lg, li);
+  if constexpr (EPI == EPI_LEAKY || EPI == EPI_MASK) {
+    // The activations of the 64 x 64 tile go through LDS (the A buffers are
+    // free after the last barrier), so that both C and its transpose Ct are
+    // written as 16-byte row chunks.
+    constexpr int SO = 64 + 8;  // row stride of the output tile (elements)
+    static_assert(64 * SO <= 2 * 64 * SK, "output tile fits in the A buffers");
+    T* Ts = &As[0][0];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int jl = wj + 16 * t + li, j = j0 + jl;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int il = wi + 16 * s + 4 * lg + r, i = i0 + il;
+          float v = acc[s][t][r];
+          if constexpr (EPI == EPI_LEAKY) {
+            v += j < a.N ? a.bias[j] : 0.f;
+            v = v > 0.f ? v : kLeakySlope * v;
+          } else {
+            const float m = (i < a.M && j < a.N)
+                                ? (float)static_cast<const T*>(a.mask)[(long long)i * a.ldc + j]
+                                : 0.f;
+            v = m > 0.f ? v : kLeakySlope * v;
+          }
+          Ts[il * SO + jl] = to_op<P>(v);
+        }
+      }
+    __syncthreads();
+    T* C = static_cast<T*>(a.C);
+    T* Ct = static_cast<T*>(a.Ct);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = tid + 256 * h, row = c >> 3, ch = (c & 7) * 8;
+      // C: row i0 + row, columns j0 + ch .. + 7
+      if (i0 + row < a.M && j0 + ch < a.N)
+        *reinterpret_cast<u4*>(C + (long long)(i0 + row) * a.ldc + j0 + ch) =
+            *reinterpret_cast<const u4*>(Ts + row * SO + ch);
+      // Ct: row j0 + row of the transpose, columns i0 + ch .. + 7
+      if (Ct && j0 + row < a.N && i0 + ch < a.M) {
+        T v8[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v8[e] = Ts[(ch + e) * SO + row];
+        *reinterpret_cast<u4*>(Ct + (long long)(j0 + row) * a.ldct + i0 + ch) =
+            __builtin_bit_cast(u4, v8);
+      }
+    }
+  } else {
+    gemm_epilogue<P, EPI>(a, acc, i0 + wi, j0 + wj, lg, li);
+  }
 }
 
 // dtheta[p] += sum over the nsplit slabs (fixed order) of the padded weight
