@@ -1,0 +1,116 @@
+"""Degenerate grids through the C ABI against the FP64 oracle: periodic
+dimensions one node wide (a population streams back onto its own node), a
+single node, and rows shorter than the 64-node work item.  Every collision
+kind (BGK, the tanh network in fp32 and bf16, the SI's LeakyReLU network,
+Smagorinsky) and the adjoint; plus the rejection of a step count below one."""
+import numpy as np
+import pytest
+
+import oracle
+from lbm_cases import lib_config, params, random_state, rel_l2, to_canonical, to_shifted
+from paper_2403_18466_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SHAPES = [("D2Q9", (1, 1, 5)), ("D2Q9", (1, 4, 1)), ("D2Q9", (1, 1, 1)),
+          ("D3Q19", (1, 1, 1)), ("D3Q19", (2, 1, 3)), ("D3Q19", (1, 3, 1))]
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_18466_amd import lbm as m
+    m.load_library()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def run_gpu(lbm, ocfg, g0, theta, nsteps, prec="fp32"):
+    L = lbm.Lattice(lib_config(ocfg, prec))
+    out = L.step(dev(to_shifted(g0, ocfg.lattice)), dev(theta) if theta is not None else None,
+                 nsteps)
+    res = to_canonical(host(out), ocfg.lattice)
+    L.close()
+    return res
+
+
+@pytest.mark.parametrize("lat,shape", SHAPES)
+def test_bgk_and_smagorinsky(lbm, lat, shape):
+    nz, ny, nx = shape
+    for kw in ({}, dict(collision="smagorinsky", smag_cs=0.17)):
+        ocfg = oracle.Config(lattice=lat, nx=nx, ny=ny, nz=nz, batch=2, tau=0.56, **kw)
+        g0 = random_state(ocfg, 31, scale=0.01)
+        want = oracle.run(ocfg, g0, None, 6)
+        got = run_gpu(lbm, ocfg, g0, None, 6)
+        assert rel_l2(got, want) < 1e-5, (kw, rel_l2(got, want))
+
+
+@pytest.mark.parametrize("lat,shape", SHAPES)
+def test_tanh_network(lbm, lat, shape):
+    nz, ny, nx = shape
+    ocfg = oracle.Config(lattice=lat, nx=nx, ny=ny, nz=nz, batch=2, tau=0.55, hidden=64,
+                         out_scale=0.25)
+    theta = params(ocfg.Q, 64, seed=32, kind="random")
+    g0 = random_state(ocfg, 33, scale=0.03)
+    want = oracle.run(ocfg, g0, theta.astype(np.float64), 3)
+    got = run_gpu(lbm, ocfg, g0, theta, 3)
+    assert rel_l2(got, want) < 1e-5
+    # bf16 operands: one step against the emulated rounding, within the
+    # bars of the full-size tests
+    oq = oracle.Config(lattice=lat, nx=nx, ny=ny, nz=nz, batch=2, tau=0.55, hidden=64,
+                       out_scale=0.25, quant="bf16")
+    emu = oracle.step(oq, g0, theta.astype(np.float64))
+    exact = oracle.step(ocfg, g0, theta.astype(np.float64))
+    got = run_gpu(lbm, oq, g0, theta, 1, prec="bf16")
+    upd = np.abs(exact - g0).max()
+    assert np.abs(got - emu).max() / upd < 2e-3
+
+
+@pytest.mark.parametrize("lat,shape", SHAPES)
+def test_paper_network(lbm, lat, shape):
+    nz, ny, nx = shape
+    ocfg = oracle.Config(lattice=lat, nx=nx, ny=ny, nz=nz, batch=2, tau=0.55, hidden=300,
+                         net="paper", out_scale=0.25)
+    theta = inputs.random_params_net(inputs.net_widths(ocfg.Q, 0, "paper"), 34, scale=0.05)
+    g0 = random_state(ocfg, 35, scale=0.03)
+    want = oracle.run(ocfg, g0, theta.astype(np.float64), 2)
+    got = run_gpu(lbm, ocfg, g0, theta.astype(np.float32), 2)
+    assert rel_l2(got, want) < 1e-5
+
+
+@pytest.mark.parametrize("lat,shape", SHAPES)
+def test_adjoint(lbm, lat, shape):
+    nz, ny, nx = shape
+    ocfg = oracle.Config(lattice=lat, nx=nx, ny=ny, nz=nz, batch=2, tau=0.55, hidden=32,
+                         out_scale=0.25)
+    theta = params(ocfg.Q, 32, seed=36, kind="random")
+    g = random_state(ocfg, 37, scale=0.03)
+    lam1 = random_state(ocfg, 38, scale=1.0)
+    want, wdth = oracle.step_adjoint(ocfg, g, lam1, theta.astype(np.float64))
+    L = lbm.Lattice(lib_config(ocfg, "fp32"))
+    lam0, dth = L.step_backward(dev(to_shifted(g, lat)), dev(theta), dev(to_shifted(lam1, lat)))
+    got = to_canonical(host(lam0), lat)
+    gdth = host(dth)
+    L.close()
+    assert rel_l2(got, want) < 1e-5
+    assert rel_l2(gdth, wdth) < 1e-5
+
+
+def test_step_count_below_one_rejected(lbm):
+    cfg = lbm.Config(nx=8, ny=8)
+    L = lbm.Lattice(cfg)
+    A = L.empty_state()
+    B = L.empty_state()
+    with pytest.raises(RuntimeError):
+        lbm.lbm_step(L.ctx, cfg, A, B, None, 0)
+    L.close()
