@@ -45,6 +45,19 @@ ACT_CYCLES_PER_LUP = (TANH_PER_LUP * (TRANS_PER_TANH / TRANS_LANES + 2 / FP32_LA
 ACT_PEAK_LUPS = SIMD_CYCLES / ACT_CYCLES_PER_LUP
 
 
+# The adjoint step (H = 64, D2Q9): it reads A^n (pulled) and lam^{n+1} and
+# writes lam^n (pushed), 3 x 36 B; its network work is the forward recompute
+# (W1, W2), the data gradient (W3^T, W2^T, W1^T) and the weight gradients
+# (dW3, dW2, dW1): 2 x (5 x 64 x 9 + 3 x 64 x 64) flops.  Its minimal ALU work
+# adds to the forward's activation the tanh derivative 1 - t^2 times the
+# incoming gradient (2 FP32 ops for each of the 128 hidden values) and the
+# conversion of d1, d2 to the operand format (64 packed conversions).
+ADJ_BYTES_PER_LUP = 108
+ADJ_FLOP_PER_LUP = 2 * (5 * 64 * 9 + 3 * 64 * 64)
+ADJ_ACT_CYCLES_PER_LUP = ACT_CYCLES_PER_LUP + TANH_PER_LUP * 2 / FP32_LANES + TANH_PER_LUP / 2 / FP32_LANES
+ADJ_ACT_PEAK_LUPS = SIMD_CYCLES / ADJ_ACT_CYCLES_PER_LUP
+
+
 # HBM bytes per launch of the bf16 step from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # each scaled by the factor a plain copy of known size gives (2.000 / 1.000);
 # None until taken for the current kernel (profiles/).
@@ -481,11 +494,22 @@ def main():
         for p, v in tr.items():
             print(f"# training step {p}: {v['train_step_ms']:.2f} ms, adjoint "
                   f"{v['adjoint_mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        lups = tr["bf16"]["adjoint_mlups"] * 1e6
         result["training"] = {"workload": "8 x 256^2 D2Q9, 32 unrolled steps, checkpoint every 8, "
                                           "H=64, forward + recompute + adjoint + Adam",
                               **{p: v for p, v in tr.items()},
                               "bf16_over_fp32_step_time": tr["fp32"]["train_step_ms"] /
-                              tr["bf16"]["train_step_ms"]}
+                              tr["bf16"]["train_step_ms"],
+                              "adjoint_roofline": {
+                                  "kernel": "nlbm_backward_kernel<D2Q9, 64, bf16>",
+                                  "bound": "alu", "achieved": lups / 1e9,
+                                  "peak": ADJ_ACT_PEAK_LUPS / 1e9,
+                                  "unit": "GLUP/s (activation ALU ceiling of the adjoint: the "
+                                          "forward's 52 SIMD-cycles per LUP plus 128 tanh "
+                                          "derivatives x 2 FP32 and 64 conversions)",
+                                  "frac": lups / ADJ_ACT_PEAK_LUPS,
+                                  "hbm_frac": ADJ_BYTES_PER_LUP * lups / HBM_PEAK,
+                                  "mfma_frac": ADJ_FLOP_PER_LUP * lups / 2.5e15}}
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
