@@ -389,7 +389,50 @@ def cpu_baseline():
     dt = time.perf_counter() - t0
     return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"{steps} step(s) of the fp64 oracle on a {n}x{n} field of the same "
-                      f"workload (same network, tau, init recipe), serial C on one host thread"}
+                      f"workload (same network, tau, init recipe), serial C on one host thread",
+            "rows": oracle_rows()}
+
+
+def oracle_rows():
+    """The fp64 oracle on small samples of the other rows' workloads (one
+    host thread, a fraction of a second to a few seconds each), in MLUPS,
+    for context beside the GPU figures."""
+    import numpy as np
+
+    import oracle
+    from paper_2403_18466_amd import inputs
+
+    def rate(cfg, theta, adjoint=False, reps=1):
+        g = np.random.default_rng(0).normal(0.0, 0.01, cfg.state_shape)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            if adjoint:
+                oracle.step_adjoint(cfg, g, g, theta)
+            else:
+                g = oracle.step(cfg, g, theta)
+        nodes = cfg.nx * cfg.ny * cfg.nz * cfg.batch
+        return nodes * reps / (time.perf_counter() - t0) / 1e6
+
+    th9 = inputs.glorot_params(9, HIDDEN, seed=1).astype(np.float64)
+    th19 = inputs.glorot_params(19, HIDDEN, seed=1).astype(np.float64)
+    thw = inputs.glorot_params_net(inputs.net_widths(19, 0, "paper"), 1).astype(np.float64)
+    rows = {
+        "bgk_d2q9": (oracle.Config(nx=1024, ny=1024, tau=TAU), None, False),
+        "smagorinsky_d2q9": (oracle.Config(nx=512, ny=512, tau=TAU, collision="smagorinsky",
+                                           smag_cs=SMAG_CS), None, False),
+        "adjoint_d2q9_h64": (oracle.Config(nx=256, ny=256, tau=0.50125, hidden=HIDDEN,
+                                           out_scale=2.0 ** -10), th9, True),
+        "nlbm_d3q19_h64": (oracle.Config(lattice="D3Q19", nx=48, ny=48, nz=48, tau=TAU,
+                                         hidden=HIDDEN, out_scale=S_OUT), th19, False),
+        "wide_d3q19": (oracle.Config(lattice="D3Q19", nx=16, ny=16, nz=16, tau=TAU, hidden=300,
+                                     net="paper", out_scale=S_OUT), thw, False),
+    }
+    out = {}
+    for name, (cfg, th, adj) in rows.items():
+        shape = "x".join(str(v) for v in (cfg.nx, cfg.ny) + ((cfg.nz,) if cfg.nz > 1 else ()))
+        out[name] = {"mlups": rate(cfg, th, adj), "sample": f"one {'adjoint ' if adj else ''}step "
+                     f"on {shape}"}
+    return out
 
 
 def main():
