@@ -136,3 +136,58 @@ def test_d3q19_256_cubed_one_step_sampled():
           f"emulated rounding / |update| {gap:.2e}")
     assert e_state < 1e-4 and e_upd < 0.5 * gap
     L.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_d3q19_256_cubed_adjoint_sampled(prec):
+    """One adjoint step at D3Q19 256^3 (the 3-D workload, 19->64->64->19 tanh,
+    s_out 2^-6) in the launch configuration bench.py times, on sampled nodes:
+    the adjoint is node-local (lam^n_q(x - c_q) = J_C(g(x))^T mu(x), mu(x) =
+    lam^{n+1}(x) read locally), so each sampled node is checked against the
+    oracle's adjoint of a one-node periodic grid holding that node's g and
+    mu.  fp32 within 1e-5; bf16 against the emulated rounding within the
+    bound of the small-grid adjoint test."""
+    from paper_2403_18466_amd import lbm
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    n = 256
+    c19 = np.array(oracle.tables("D3Q19")[0])
+    quant = "bf16" if prec == "bf16" else "none"
+    ocfg = oracle.Config(lattice="D3Q19", nx=n, ny=n, nz=n, tau=0.51, hidden=64,
+                         out_scale=2.0 ** -6)
+    u = inputs.solenoidal_spectrum_velocity((n, n, n), 4.0, 0.04, seed=0)
+    g = oracle.init_equilibrium(ocfg, np.ones((1, n, n, n)), u[None])
+    del u
+    g32 = g.astype(np.float32)
+    del g
+    A = np.empty_like(g32)
+    for q in range(19):
+        A[0, q] = np.roll(g32[0, q], shift=(-c19[q, 2], -c19[q, 1], -c19[q, 0]), axis=(0, 1, 2))
+    theta = inputs.glorot_params(19, 64, seed=1)
+    L = lbm.Lattice(lib_config(ocfg, prec))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(40)
+    lam1 = torch.randn((1, 19, n, n, n), device="cuda", generator=gen)
+    lam0, _ = L.step_backward(torch.from_numpy(A).cuda(), torch.from_numpy(theta).cuda(), lam1)
+    del A
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(lam0).all())
+    rng = np.random.default_rng(41)
+    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 63), (255, 0, 64)] + \
+        [tuple(p) for p in rng.integers(0, n, size=(20, 3))]
+    one = oracle.Config(lattice="D3Q19", nx=1, ny=1, nz=1, tau=0.51, hidden=64,
+                        out_scale=2.0 ** -6, quant=quant)
+    th64 = theta.astype(np.float64)
+    got, want = [], []
+    for z, y, x in pts:
+        gg = g32[0, :, z, y, x].astype(np.float64).reshape(1, 19, 1, 1, 1)
+        mu = lam1[0, :, z, y, x].cpu().numpy().astype(np.float64).reshape(1, 19, 1, 1, 1)
+        w, _ = oracle.step_adjoint(one, gg, mu, th64)
+        want.append(w[0, :, 0, 0, 0])
+        got.append([lam0[0, q, (z - c19[q, 2]) % n, (y - c19[q, 1]) % n,
+                         (x - c19[q, 0]) % n].item() for q in range(19)])
+    got, want = np.array(got), np.array(want)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"D3Q19 256^3 adjoint {prec}: sampled lam rel L2 {err:.2e}")
+    assert err < (1e-5 if prec == "fp32" else 2e-3)
+    L.close()
