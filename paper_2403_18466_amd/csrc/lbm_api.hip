@@ -328,13 +328,16 @@ lbm_status launch_nlbm(lbm_ctx* ctx, const float* Ain, float* Aout, const float*
   int nxc = (G.nx + 63) / 64;
   long long nitems = (long long)nxc * G.ny * G.nz * G.batch;
   if (nitems >= (1LL << 31)) return fail(LBM_ERR_INVALID, "too many work items");
-  unsigned blocks = 0;
-  lbm_status st = persistent_blocks(ctx, nlbm_step_kernel<L, H, P>, 4, nitems, blocks);
-  if (st != LBM_OK) return st;
   const lbm_config& c = ctx->cfg;
-  hipLaunchKernelGGL((nlbm_step_kernel<L, H, P>), dim3(blocks), dim3(256), 0, s, Ain, Aout,
-                     theta, G, force_of(c), (float)c.rho0, (float)(1.0 / c.tau),
-                     (float)(c.out_scale / c.tau), (int)nitems, nxc);
+  // forced and unforced instances: the unforced one needs fewer registers
+  const bool forced = c.force_kind != LBM_FORCE_NONE;
+  const auto kernel = forced ? nlbm_step_kernel<L, H, P, true> : nlbm_step_kernel<L, H, P, false>;
+  unsigned blocks = 0;
+  lbm_status st = persistent_blocks(ctx, kernel, 4, nitems, blocks);
+  if (st != LBM_OK) return st;
+  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, Ain, Aout, theta, G, force_of(c),
+                     (float)c.rho0, (float)(1.0 / c.tau), (float)(c.out_scale / c.tau),
+                     (int)nitems, nxc);
   LBM_LAUNCHED("nlbm_step_kernel");
   return LBM_OK;
 }
