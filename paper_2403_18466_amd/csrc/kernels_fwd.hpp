@@ -493,6 +493,14 @@ struct StepLds {
   static constexpr int YQ = (L::Q + 3) / 4 * 4;
   static constexpr int SX = YC + YQ + 4;  // row stride (floats)
   static constexpr int per_wave = 64 * SX;
+  // the layer-3 bias sits in the padding columns of the first 4 QB rows
+  // (row 4 ob + g holds b3[16 ob + 4 g .. + 3]), not in registers
+  static constexpr int B3 = YC + YQ;
+  // wavefronts per SIMD the compiler must leave room for: three for the
+  // unforced 16-bit D3Q19 instance, else no constraint
+  static constexpr int min_waves(int prec, bool forced) {
+    return (L::Q == 19 && prec == P_BF16 && !forced) ? 3 : 1;
+  }
 };
 
 // FORCED: the body force of eq. fext is applied (Force::kind != 0).  The
@@ -500,7 +508,8 @@ struct StepLds {
 // 64-bit argument reduction): 116 instead of 150 registers per lane for the
 // 16-bit D2Q9 instance, 176 instead of 233 for D3Q19.
 template <class L, int H, int P, bool FORCED>
-__global__ __launch_bounds__(256) void nlbm_step_kernel(const float* __restrict__ Ain,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    StepLds<L, H>::min_waves(P, FORCED)))) void nlbm_step_kernel(const float* __restrict__ Ain,
                                                         float* __restrict__ Aout,
                                                         const float* __restrict__ theta, Grid G,
                                                         Force Fc, float rho0, float omega,
@@ -532,6 +541,13 @@ __global__ __launch_bounds__(256) void nlbm_step_kernel(const float* __restrict_
   // the bias of layer 1, then zeros
 #pragma unroll
   for (int k = Q; k < LD::YC; ++k) X[lane * LD::SX + k] = k == Q ? 1.f : 0.f;
+  if (lane < 4 * S::QB) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int q = 4 * lane + r;
+      X[lane * LD::SX + LD::B3 + r] = q < Q ? theta[S::ob3 + q] : 0.f;
+    }
+  }
 
   ItemWalk cur, nxt;
   cur.start(it0, nxc, G);
@@ -566,7 +582,8 @@ __global__ __launch_bounds__(256) void nlbm_step_kernel(const float* __restrict_
         h2[ob] = to_frag<P>(tanh4<P>(mma_row<P, S::HB>(W.b2[ob], W.w2[ob], h1)));
 #pragma unroll
       for (int ob = 0; ob < S::QB; ++ob) {
-        const f4 y = mma_row<P, S::HB>(W.b3[ob], W.w3[ob], h2);
+        const f4 b3 = *reinterpret_cast<const f4*>(X + (4 * ob + lg) * LD::SX + LD::B3);
+        const f4 y = mma_row<P, S::HB>(b3, W.w3[ob], h2);
         if (16 * ob + 4 * lg < LD::YQ)
           *reinterpret_cast<f4*>(Y + nrow * LD::SX + 16 * ob + 4 * lg) = y;
       }
