@@ -135,7 +135,6 @@ __global__ __launch_bounds__(256) void bgk_backward_kernel(const float* __restri
 // if it had no work) to part[wave][param]; grad_reduce_kernel sums them in a
 // fixed order.
 // ---------------------------------------------------------------------------
-constexpr unsigned bwd_blocks(int ncu) { return (unsigned)ncu; }
 
 // 16-node groups differentiated together (two wherever their transpose
 // tiles fit in the LDS; the D3Q19 instances fall back to one)
@@ -167,6 +166,44 @@ struct BwdLayout {
   static constexpr int per_wave = wave_floats(NGP);
 };
 
+// Block-shared transposed weight fragments for the backward contractions,
+// fragment-major (fragment f of lane l at w[64 f + l]): W3^T (HB x QB
+// fragments), W2^T (HB x HB), W1^T (KX x HB).  W2 and W1 are the tanh
+// layers: for bf16 / fp16 their fragments hold c W rounded, like the
+// forward's, and the products are scaled back by 1/c.
+template <class L, int H, int P>
+__device__ inline void load_transposed_weights(typename Frag<P>::T* w,
+                                               const float* __restrict__ theta) {
+  using S = Shape<L::Q, H>;
+  constexpr int Q = L::Q;
+  constexpr int NF3 = S::HB * S::QB, NF2 = S::HB * S::HB, NF = NF3 + NF2 + S::KX * S::HB;
+  constexpr float sc = tanh_weight_scale<P>();
+  for (int e = threadIdx.x; e < NF * 64; e += blockDim.x) {
+    const int f = e >> 6, l = e & 63, g = l >> 4, i = l & 15;
+    f4 v;
+    if (f < NF3) {  // W3^T: row h = 16 ob + i, k = q = 16 qc + 4 g + r
+      const int ob = f / S::QB, qc = f % S::QB;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int q = 16 * qc + 4 * g + r, h = 16 * ob + i;
+        v[r] = q < Q ? theta[S::oW3 + q * H + h] : 0.f;
+      }
+    } else if (f < NF3 + NF2) {  // W2^T: row h = 16 ob + i, k = o = 16 c + 4 g + r
+      const int ff = f - NF3, ob = ff / S::HB, c = ff % S::HB;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = sc * theta[S::oW2 + (16 * c + 4 * g + r) * H + 16 * ob + i];
+    } else {  // W1^T: row k = 16 c + i (input index), k' = o = 16 ob + 4 g + r
+      const int ff = f - NF3 - NF2, c = ff / S::HB, ob = ff % S::HB;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int k = 16 * c + i, o = 16 * ob + 4 * g + r;
+        v[r] = k < Q ? sc * theta[S::oW1 + o * Q + k] : 0.f;
+      }
+    }
+    w[e] = to_frag<P>(v);
+  }
+}
+
 template <class L, int H, int P>
 __global__ __launch_bounds__(256) void nlbm_backward_kernel(
     const float* __restrict__ A, const float* __restrict__ theta, const float* __restrict__ lam1,
@@ -182,34 +219,8 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
   const int lane = threadIdx.x & 63, lg = lane >> 4, li = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-  // Block-shared transposed weight fragments for the backward contractions.
-  // W2 and W1 are the tanh layers: for bf16 / fp16 their fragments hold
-  // c W rounded, like the forward's, and the products are scaled back by 1/c.
   constexpr float sc = tanh_weight_scale<P>();
-  for (int e = threadIdx.x; e < BL::NF * 64; e += 256) {
-    const int f = e >> 6, l = e & 63, g = l >> 4, i = l & 15;
-    f4 v;
-    if (f < BL::NF3) {  // W3^T: row h = 16 ob + i, k = q = 16 qc + 4 g + r
-      const int ob = f / S::QB, qc = f % S::QB;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int q = 16 * qc + 4 * g + r, h = 16 * ob + i;
-        v[r] = q < Q ? theta[S::oW3 + q * H + h] : 0.f;
-      }
-    } else if (f < BL::NF3 + BL::NF2) {  // W2^T: row h = 16 ob + i, k = o = 16 c + 4 g + r
-      const int ff = f - BL::NF3, ob = ff / S::HB, c = ff % S::HB;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = sc * theta[S::oW2 + (16 * c + 4 * g + r) * H + 16 * ob + i];
-    } else {  // W1^T: row k = 16 c + i (input index), k' = o = 16 ob + 4 g + r
-      const int ff = f - BL::NF3 - BL::NF2, c = ff / S::HB, ob = ff % S::HB;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int k = 16 * c + i, o = 16 * ob + 4 * g + r;
-        v[r] = k < Q ? sc * theta[S::oW1 + o * Q + k] : 0.f;
-      }
-    }
-    wbk[e] = to_frag<P>(v);
-  }
+  load_transposed_weights<L, H, P>(wbk, theta);
   __syncthreads();
 
   float* X = lds + wave * BL::per_wave;  // [64][SX] network input x0
@@ -475,85 +486,511 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
     }
   }
 
-  // Parameter-gradient partials: the four waves of the block are summed in
-  // LDS in wave order (the tiles are free once every wave has left the item
-  // loop), then the block writes one partial vector part[block][param].
+  // Parameter-gradient partials: every wave writes its full vector to its
+  // own LDS row (the tiles are free once every wave has left the item loop),
+  // then the block sums the four rows in wave order and writes one partial
+  // vector part[block][param].
   __syncthreads();
-  float* red = lds;  // S::n floats, fits in the per-wave tiles of the block
-  static_assert(S::n <= 4 * BL::per_wave, "reduction buffer");
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-      auto put = [&](int idx, float v) { red[idx] = w == 0 ? v : red[idx] + v; };
+  static_assert(4 * S::n <= 4 * BL::per_wave, "reduction buffer");
+  {
+    float* red = lds + wave * S::n;
 #pragma unroll
-      for (int ob = 0; ob < S::HB; ++ob) {
+    for (int ob = 0; ob < S::HB; ++ob) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int o = 16 * ob + 4 * lg + r;
+      for (int r = 0; r < 4; ++r) {
+        const int o = 16 * ob + 4 * lg + r;
 #pragma unroll
-          for (int c = 0; c < S::KX; ++c) {
-            const int k = 16 * c + li;
-            if (k < Q) put(S::oW1 + o * Q + k, dW1[ob][c][r]);
-            else if (k == Q) put(S::ob1 + o, dW1[ob][c][r]);
-          }
-#pragma unroll
-          for (int c = 0; c < S::HB; ++c) put(S::oW2 + o * H + 16 * c + li, dW2[ob][c][r]);
-          float sb = db2[ob][r];
-          sb += __shfl_xor(sb, 8);
-          sb += __shfl_xor(sb, 4);
-          sb += __shfl_xor(sb, 2);
-          sb += __shfl_xor(sb, 1);
-          if (li == 0) put(S::ob2 + o, sb);
-        }
-      }
-#pragma unroll
-      for (int qc = 0; qc < S::QB; ++qc)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int q = 16 * qc + 4 * lg + r;
-#pragma unroll
-          for (int c = 0; c < S::HB; ++c)
-            if (q < Q) put(S::oW3 + q * H + 16 * c + li, dW3[qc][c][r]);
+        for (int c = 0; c < S::KX; ++c) {
+          const int k = 16 * c + li;
+          if (k < Q) red[S::oW1 + o * Q + k] = dW1[ob][c][r];
+          else if (k == Q) red[S::ob1 + o] = dW1[ob][c][r];
         }
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        float sq = db3[q];
-        sq += __shfl_xor(sq, 32);
-        sq += __shfl_xor(sq, 16);
-        sq += __shfl_xor(sq, 8);
-        sq += __shfl_xor(sq, 4);
-        sq += __shfl_xor(sq, 2);
-        sq += __shfl_xor(sq, 1);
-        if (lane == 0) put(S::ob3 + q, sq);
+        for (int c = 0; c < S::HB; ++c) red[S::oW2 + o * H + 16 * c + li] = dW2[ob][c][r];
+        float sb = db2[ob][r];
+        sb += __shfl_xor(sb, 8);
+        sb += __shfl_xor(sb, 4);
+        sb += __shfl_xor(sb, 2);
+        sb += __shfl_xor(sb, 1);
+        if (li == 0) red[S::ob2 + o] = sb;
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int qc = 0; qc < S::QB; ++qc)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = 16 * qc + 4 * lg + r;
+#pragma unroll
+        for (int c = 0; c < S::HB; ++c)
+          if (q < Q) red[S::oW3 + q * H + 16 * c + li] = dW3[qc][c][r];
+      }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      float sq = db3[q];
+      sq += __shfl_xor(sq, 32);
+      sq += __shfl_xor(sq, 16);
+      sq += __shfl_xor(sq, 8);
+      sq += __shfl_xor(sq, 4);
+      sq += __shfl_xor(sq, 2);
+      sq += __shfl_xor(sq, 1);
+      if (lane == 0) red[S::ob3 + q] = sq;
+    }
   }
+  __syncthreads();
   float* pb = part + (size_t)blockIdx.x * S::n;
-  for (int i = threadIdx.x; i < S::n; i += 256) pb[i] = red[i];
+  for (int i = threadIdx.x; i < S::n; i += 256)
+    pb[i] = ((lds[i] + lds[S::n + i]) + lds[2 * S::n + i]) + lds[3 * S::n + i];
+}
+
+// ---------------------------------------------------------------------------
+// Cooperative adjoint of the learned-collision step (16-bit D2Q9 networks).
+//
+// The kernel above keeps all parameter-gradient accumulators of the network
+// and the forward weights in every wavefront (about 150 registers at
+// H = 64) and fits one wavefront per SIMD.  Here the eight wavefronts of a
+// workgroup (two per SIMD) take one 16-node group each per step and split
+// the 16 x 16 weight-gradient tiles between them.  After the forward
+// recompute and the backward data path of its group, a wavefront writes the
+// group's gradient operands in contraction layout (the node index as K,
+// 16-bit) to its LDS slot; after a workgroup barrier each wavefront
+// accumulates its own TPW tiles over the 128 nodes of the eight slots.  The
+// network weights are read from LDS.  The contraction order is fixed, so
+// the result is reproducible.
+//
+// Slot fragment layout: fragment f holds, for logical lane l = i + 16 g,
+// the four 16-bit values A[i][4 g + r] (feature i of the fragment's 16,
+// nodes 4 g + r of the group) at byte 512 f + 8 swz(l) + 2 r, with
+// swz(l) = l ^ ((l >> 4) & 3).  The swizzle spreads the transposing 16-bit
+// writes (one feature row at a time from the D layout) over all 32 banks.
+// ---------------------------------------------------------------------------
+template <class L, int H, int P>
+struct CoopLayout {
+  using S = Shape<L::Q, H>;
+  static constexpr int NW = 8;  // wavefronts per workgroup
+  static constexpr int NT2 = S::HB * S::HB, NT1 = S::HB * S::KX, NT3 = S::QB * S::HB;
+  static constexpr int NT = NT2 + NT1 + NT3, TPW = NT / NW;
+  // fragments of one group, in slot order
+  static constexpr int FDY = 0, FH2 = FDY + S::QB, FD2 = FH2 + S::HB, FH1 = FD2 + S::HB,
+                       FD1 = FH1 + S::HB, FX0 = FD1 + S::HB, NFR = FX0 + S::KX;
+  static constexpr int XS = 16 * S::KX + 4;                             // x0 row (16-bit elements)
+  static constexpr int SD = 16 * (S::QB > S::KX ? S::QB : S::KX) + 4;  // dy / dx row (floats)
+  // weight fragments: transposed for the backward products, then W1 and W2
+  static constexpr int NFB = S::HB * S::QB + S::HB * S::HB + S::KX * S::HB;
+  static constexpr int NFF = S::HB * S::KX + S::HB * S::HB;
+  static constexpr int x_bytes = 64 * XS * 2, d_bytes = 64 * SD * 4, slot_bytes = NFR * 512;
+  static constexpr int wave_bytes = x_bytes + d_bytes + slot_bytes;
+  static constexpr int bytes = (NFB + NFF) * 512 + H * 4 + NW * wave_bytes;
+  static constexpr bool ok = P != P_F32 && NT % NW == 0 && bytes <= 160 * 1024 &&
+                             (S::n + NW * (H + L::Q)) * 4 <= NW * wave_bytes;
+  // tile t: dW2 (ob, ib) for t < NT2, then dW1|db1 (ob, c), then dW3 (qc, ib)
+  static constexpr int kind(int t) { return t < NT2 ? 2 : (t < NT2 + NT1 ? 1 : 3); }
+  static constexpr int fa(int t) {
+    return t < NT2 ? FD2 + t / S::HB
+                   : (t < NT2 + NT1 ? FD1 + (t - NT2) / S::KX : FDY + (t - NT2 - NT1) / S::HB);
+  }
+  static constexpr int fb(int t) {
+    return t < NT2 ? FH1 + t % S::HB
+                   : (t < NT2 + NT1 ? FX0 + (t - NT2) % S::KX : FH2 + (t - NT2 - NT1) % S::HB);
+  }
+};
+
+// Workgroups of the adjoint launch (one per compute unit); the workspace
+// holds one partial gradient vector per workgroup.
+constexpr unsigned bwd_blocks(int ncu) { return (unsigned)ncu; }
+
+// Forward weight fragments in LDS, fragment-major: W1 (ob, c) at ob KX + c
+// with the layer-1 bias as input column Q, then W2 (ob, c) at
+// HB KX + ob HB + c; both scaled by the tanh argument scale.
+template <class L, int H, int P>
+__device__ inline void load_forward_weights(typename Frag<P>::T* w, const float* __restrict__ th) {
+  using S = Shape<L::Q, H>;
+  constexpr int N1 = S::HB * S::KX, NFF = N1 + S::HB * S::HB;
+  constexpr float sc = tanh_weight_scale<P>();
+  for (int e = threadIdx.x; e < NFF * 64; e += blockDim.x) {
+    const int f = e >> 6, l = e & 63, g = l >> 4, i = l & 15;
+    f4 v;
+    if (f < N1) {
+      const int o = 16 * (f / S::KX) + i, c = f % S::KX;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int k = 16 * c + 4 * g + r;
+        v[r] = sc * (k < S::Q ? th[S::oW1 + o * S::Q + k] : (k == S::Q ? th[S::ob1 + o] : 0.f));
+      }
+    } else {
+      const int ff = f - N1, o = 16 * (ff / S::HB) + i, c = ff % S::HB;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = sc * th[S::oW2 + o * S::H + 16 * c + 4 * g + r];
+    }
+    w[e] = to_frag<P>(v);
+  }
+}
+
+// acc[j] += the product of tile W TPW + j over the slots (the nodes of
+// slots 2p and 2p + 1 form the K = 32 of one matrix-core instruction).
+template <class CL, int P, int W>
+__device__ inline void coop_tiles(f4 (&acc)[CL::TPW], const unsigned char* slots, int rdo) {
+  using Fr = typename Frag<P>::T;
+  auto frag = [&](int w, int f) {
+    return *reinterpret_cast<const Fr*>(slots + w * CL::wave_bytes + f * 512 + rdo);
+  };
+#pragma unroll
+  for (int j = 0; j < CL::TPW; ++j) {
+    const int t = W * CL::TPW + j;
+#pragma unroll
+    for (int p = 0; p < CL::NW; p += 2)
+      acc[j] = mma_pair<P>(acc[j], frag(p, CL::fa(t)), frag(p + 1, CL::fa(t)),
+                           frag(p, CL::fb(t)), frag(p + 1, CL::fb(t)));
+  }
+}
+
+// Tiles of wavefront W to their parameter entries (D layout: lane l holds
+// rows 4 (l / 16) + r of column l % 16).
+template <class CL, int W>
+__device__ inline void coop_put(const f4 (&acc)[CL::TPW], float* red, int lg, int li) {
+  using S = typename CL::S;
+#pragma unroll
+  for (int j = 0; j < CL::TPW; ++j) {
+    const int t = W * CL::TPW + j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float v = acc[j][r];
+      if (CL::kind(t) == 2) {
+        const int o = 16 * (t / S::HB) + 4 * lg + r, i = 16 * (t % S::HB) + li;
+        red[S::oW2 + o * S::H + i] = v;
+      } else if (CL::kind(t) == 1) {
+        const int u = t - CL::NT2, o = 16 * (u / S::KX) + 4 * lg + r, k = 16 * (u % S::KX) + li;
+        if (k < S::Q) red[S::oW1 + o * S::Q + k] = v;
+        else if (k == S::Q) red[S::ob1 + o] = v;
+      } else {
+        const int u = t - CL::NT2 - CL::NT1, q = 16 * (u / S::HB) + 4 * lg + r,
+                  i = 16 * (u % S::HB) + li;
+        if (q < S::Q) red[S::oW3 + q * S::H + i] = v;
+      }
+    }
+  }
+}
+
+// Dispatch on the (wave-uniform) wavefront index.
+template <class CL, int P, int W = 0>
+__device__ inline void coop_tiles_of(int wave, f4 (&acc)[CL::TPW], const unsigned char* slots,
+                                     int rdo) {
+  if constexpr (W + 1 < CL::NW) {
+    if (wave == W) coop_tiles<CL, P, W>(acc, slots, rdo);
+    else coop_tiles_of<CL, P, W + 1>(wave, acc, slots, rdo);
+  } else {
+    coop_tiles<CL, P, W>(acc, slots, rdo);
+  }
+}
+template <class CL, int W = 0>
+__device__ inline void coop_put_of(int wave, const f4 (&acc)[CL::TPW], float* red, int lg, int li) {
+  if constexpr (W + 1 < CL::NW) {
+    if (wave == W) coop_put<CL, W>(acc, red, lg, li);
+    else coop_put_of<CL, W + 1>(wave, acc, red, lg, li);
+  } else {
+    coop_put<CL, W>(acc, red, lg, li);
+  }
+}
+
+template <class L, int H, int P>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void
+nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__ theta,
+                          const float* __restrict__ lam1, float* __restrict__ lam0,
+                          float* __restrict__ part, Grid G, Force Fc, float rho0, float omega,
+                          float knn, int nitems, int nxc) {
+  using S = Shape<L::Q, H>;
+  using CL = CoopLayout<L, H, P>;
+  using Fr = typename Frag<P>::T;
+  constexpr int Q = L::Q, NW = CL::NW;
+  static_assert(CL::ok, "cooperative adjoint: precision or LDS budget");
+  __shared__ Fr wts[(CL::NFB + CL::NFF) * 64];
+  __shared__ __attribute__((aligned(16))) float b2s[H];  // c b2 (the layer-2 bias)
+  __shared__ __attribute__((aligned(16))) unsigned char wl[NW * CL::wave_bytes];
+
+  const int lane = threadIdx.x & 63, lg = lane >> 4, li = lane & 15;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+  constexpr float sc = tanh_weight_scale<P>();
+  load_transposed_weights<L, H, P>(wts, theta);
+  load_forward_weights<L, H, P>(wts + CL::NFB * 64, theta);
+  for (int o = threadIdx.x; o < H; o += blockDim.x) b2s[o] = sc * theta[S::ob2 + o];
+  __syncthreads();
+  const Fr* W3T = wts;
+  const Fr* W2T = wts + S::HB * S::QB * 64;
+  const Fr* W1T = wts + (S::HB * S::QB + S::HB * S::HB) * 64;
+  const Fr* W1F = wts + CL::NFB * 64;
+  const Fr* W2F = W1F + S::HB * S::KX * 64;
+
+  unsigned char* mine = wl + wave * CL::wave_bytes;
+  unsigned short* X = reinterpret_cast<unsigned short*>(mine);  // [64][XS] x0, operand format
+  float* D = reinterpret_cast<float*>(mine + CL::x_bytes);      // [64][SD] dy, then dx
+  unsigned char* slot = mine + CL::x_bytes + CL::d_bytes;
+  const unsigned char* slots = wl + CL::x_bytes + CL::d_bytes;  // slot w at w * wave_bytes
+
+  // contraction-layout addresses: this lane's read offset, and the write
+  // offsets of its four D-layout values (feature 4 lg + r, node li)
+  const int rdo = 8 * (lane ^ ((lane >> 4) & 3));
+  int wro[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) wro[r] = 8 * (4 * lg + (r ^ (li >> 2)) + 16 * (li >> 2)) + 2 * (li & 3);
+
+  // workgroup range of items; wavefront w takes item k + w of each step
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int lb = (nb % 8 == 0) ? (bid % 8) * (nb / 8) + bid / 8 : bid;
+  const int per = (nitems + nb - 1) / nb;
+  const int ib0 = min(lb * per, nitems), ib1 = min(ib0 + per, nitems);
+
+  f4 acc[CL::TPW], db2[S::HB];
+#pragma unroll
+  for (int j = 0; j < CL::TPW; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 0; a < S::HB; ++a) db2[a] = f4{0.f, 0.f, 0.f, 0.f};
+  float db3[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) db3[q] = 0.f;
+
+  const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * Q) * 4u;
+  const rsrc_t rA = make_rsrc(A, bytes), rL1 = make_rsrc(lam1, bytes),
+               rL0 = make_rsrc(lam0, bytes);
+  // items past the range enter as zeros: every product they feed is zero
+  auto load = [&](int it, float g[Q], float mu[Q]) {
+    bool act = false;
+    Item t;
+    if (it < ib1) {
+      t = locate_item(it, nxc, G, lane);
+      act = t.active;
+    }
+    if (act) {
+      gather_item<L>(rA, G, t, g);
+      load_local<L>(rL1, G, t, mu);
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) g[q] = mu[q] = 0.f;
+    }
+  };
+
+  float gc[Q], mc[Q];
+  if (ib0 < ib1) load(ib0 + wave, gc, mc);
+  for (int k = ib0; k < ib1; k += NW) {
+    const int it = k + wave;
+    const Item t = locate_item(it < ib1 ? it : ib0, nxc, G, lane);
+    const bool act = it < ib1 && t.active;
+    float F3[3] = {0.f, 0.f, 0.f};
+    if (Fc.kind != 0) body_force(Fc, G, t.x, t.y, t.z, F3);
+    float nu[Q], lam[Q];
+    collide_adjoint<L>(gc, mc, rho0, omega, F3, Fc.kind != 0, nu, lam);
+
+    // stage x0 (rounded to the operand format) and dy = k nu, node-major rows
+#pragma unroll
+    for (int c = 0; c < 4 * S::KX; ++c) {
+      f4 v;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int kk = 4 * c + r;
+        v[r] = kk < Q ? gc[kk] : (kk == Q ? 1.f : 0.f);
+      }
+      *reinterpret_cast<Fr*>(X + lane * CL::XS + 4 * c) = to_frag<P>(v);
+    }
+#pragma unroll
+    for (int c = 0; c < 4 * S::QB; ++c) {
+      f4 v;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int q = 4 * c + r;
+        float d = q < Q ? knn * nu[q] : 0.f;
+        v[r] = d;
+        if (q < Q) db3[q] += d;
+      }
+      *reinterpret_cast<f4*>(D + lane * CL::SD + 4 * c) = v;
+    }
+    wave_lds_sync();
+
+    auto put_t = [&](int f, Fr v) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        *reinterpret_cast<unsigned short*>(slot + f * 512 + wro[r]) =
+            (unsigned short)(v[r >> 1] >> (16 * (r & 1)));
+    };
+#pragma unroll 1
+    for (int jg = 0; jg < 4; ++jg) {
+      const int nrow = 16 * jg + li;
+      // Each layer's weight fragments are read from LDS as one batch, issued
+      // before the VALU work of the previous layer so that their latency
+      // overlaps it (the scheduling barriers keep the reads there).
+      f4 t1[S::HB], t2[S::HB];
+      {
+        Fr xin[S::KX], x0T[S::KX], w1[S::HB * S::KX], h1[S::HB], h2[S::HB];
+#pragma unroll
+        for (int i = 0; i < S::HB * S::KX; ++i) w1[i] = W1F[64 * i + lane];
+#pragma unroll
+        for (int c = 0; c < S::KX; ++c) {
+          xin[c] = *reinterpret_cast<const Fr*>(X + nrow * CL::XS + 16 * c + 4 * lg);
+          unsigned e[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) e[r] = X[(16 * jg + 4 * lg + r) * CL::XS + 16 * c + li];
+          x0T[c] = Fr{e[0] | (e[1] << 16), e[2] | (e[3] << 16)};
+        }
+        f4 a1[S::HB];
+#pragma unroll
+        for (int ob = 0; ob < S::HB; ++ob)
+          a1[ob] = mma_row<P, S::KX>(f4{0.f, 0.f, 0.f, 0.f}, w1 + ob * S::KX, xin);
+        Fr w2[S::HB * S::HB];
+#pragma unroll
+        for (int i = 0; i < S::HB * S::HB; ++i) w2[i] = W2F[64 * i + lane];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ob = 0; ob < S::HB; ++ob) {
+          t1[ob] = tanh4<P>(a1[ob]);
+          h1[ob] = to_frag<P>(t1[ob]);
+        }
+#pragma unroll
+        for (int ob = 0; ob < S::HB; ++ob) {
+          const f4 b2 = *reinterpret_cast<const f4*>(b2s + 16 * ob + 4 * lg);
+          t2[ob] = tanh4<P>(mma_row<P, S::HB>(b2, w2 + ob * S::HB, h1));
+          h2[ob] = to_frag<P>(t2[ob]);
+        }
+        // every wavefront has finished reading the slots of the previous step
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < S::KX; ++c)
+          *reinterpret_cast<Fr*>(slot + (CL::FX0 + c) * 512 + rdo) = x0T[c];
+#pragma unroll
+        for (int ob = 0; ob < S::HB; ++ob) {
+          put_t(CL::FH1 + ob, h1[ob]);
+          put_t(CL::FH2 + ob, h2[ob]);
+        }
+      }
+      {
+        // dy in operand layout and in contraction layout
+        Fr dyf[S::QB], w3t[S::HB * S::QB];
+#pragma unroll
+        for (int i = 0; i < S::HB * S::QB; ++i) w3t[i] = W3T[64 * i + lane];
+#pragma unroll
+        for (int qc = 0; qc < S::QB; ++qc) {
+          dyf[qc] = to_frag<P>(*reinterpret_cast<const f4*>(D + nrow * CL::SD + 16 * qc + 4 * lg));
+          f4 v;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[r] = D[(16 * jg + 4 * lg + r) * CL::SD + 16 * qc + li];
+          *reinterpret_cast<Fr*>(slot + (CL::FDY + qc) * 512 + rdo) = to_frag<P>(v);
+        }
+        // d2 = (W3^T dy) (1 - t2^2),  d1 = (W2^T d2) (1 - t1^2)
+        f4 a2[S::HB];
+#pragma unroll
+        for (int ob = 0; ob < S::HB; ++ob)
+          a2[ob] = mma_row<P, S::QB>(f4{0.f, 0.f, 0.f, 0.f}, w3t + ob * S::QB, dyf);
+        Fr w2t[S::HB * S::HB];
+#pragma unroll
+        for (int i = 0; i < S::HB * S::HB; ++i) w2t[i] = W2T[64 * i + lane];
+        __builtin_amdgcn_sched_barrier(0);
+        Fr d2f[S::HB], d1f[S::HB];
+#pragma unroll
+        for (int ob = 0; ob < S::HB; ++ob) {
+          const f4 d2 = a2[ob] * (1.f - t2[ob] * t2[ob]);
+          db2[ob] += d2;
+          d2f[ob] = to_frag<P>(d2);
+          put_t(CL::FD2 + ob, d2f[ob]);
+        }
+        f4 a3[S::HB];
+#pragma unroll
+        for (int ob = 0; ob < S::HB; ++ob)
+          a3[ob] = mma_row<P, S::HB>(f4{0.f, 0.f, 0.f, 0.f}, w2t + ob * S::HB, d2f);
+        Fr w1t[S::KX * S::HB];
+#pragma unroll
+        for (int i = 0; i < S::KX * S::HB; ++i) w1t[i] = W1T[64 * i + lane];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ob = 0; ob < S::HB; ++ob) {
+          d1f[ob] = to_frag<P>(a3[ob] * (1.f / sc) * (1.f - t1[ob] * t1[ob]));
+          put_t(CL::FD1 + ob, d1f[ob]);
+        }
+        // dx = W1^T d1 over this group's rows, whose dy has been read
+        wave_lds_sync();
+#pragma unroll
+        for (int c = 0; c < S::KX; ++c) {
+          f4 a = mma_row<P, S::HB>(f4{0.f, 0.f, 0.f, 0.f}, w1t + c * S::HB, d1f);
+          a = a * (1.f / sc);
+          *reinterpret_cast<f4*>(D + nrow * CL::SD + 16 * c + 4 * lg) = a;
+        }
+      }
+      __syncthreads();
+      // this wavefront's weight-gradient tiles over the nodes of the step
+      coop_tiles_of<CL, P>(wave, acc, slots, rdo);
+    }
+    // the next item's loads go out before this item's results
+    if (k + NW < ib1) load(it + NW, gc, mc);
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) lam[q] += D[lane * CL::SD + q];
+    if (act) scatter_item<L>(rL0, G, t, lam);
+    wave_lds_sync();
+  }
+
+  // Partial gradient of the workgroup: the tiles are disjoint between the
+  // wavefronts.  The bias sums of layers 2 and 3 are reduced within every
+  // wavefront at once, then added over the wavefronts in wave order.
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(wl);
+  float* bsum = red + S::n;  // [NW][H + Q]
+  coop_put_of<CL>(wave, acc, red, lg, li);
+#pragma unroll
+  for (int ob = 0; ob < S::HB; ++ob)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float sb = db2[ob][r];
+      sb += __shfl_xor(sb, 8);
+      sb += __shfl_xor(sb, 4);
+      sb += __shfl_xor(sb, 2);
+      sb += __shfl_xor(sb, 1);
+      if (li == 0) bsum[wave * (H + Q) + 16 * ob + 4 * lg + r] = sb;
+    }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    float sq = db3[q];
+    sq += __shfl_xor(sq, 32);
+    sq += __shfl_xor(sq, 16);
+    sq += __shfl_xor(sq, 8);
+    sq += __shfl_xor(sq, 4);
+    sq += __shfl_xor(sq, 2);
+    sq += __shfl_xor(sq, 1);
+    if (lane == 0) bsum[wave * (H + Q) + H + q] = sq;
+  }
+  __syncthreads();
+  if (threadIdx.x < H + Q) {
+    const int i = threadIdx.x;
+    float sum = bsum[i];
+    for (int w = 1; w < NW; ++w) sum += bsum[w * (H + Q) + i];
+    red[i < H ? S::ob2 + i : S::ob3 + (i - H)] = sum;
+  }
+  __syncthreads();
+  float* pb = part + (size_t)blockIdx.x * S::n;
+  for (int i = threadIdx.x; i < S::n; i += blockDim.x) pb[i] = red[i];
 }
 
 // dtheta[p] += sum over the nb block partials part[b][p], in float64.
-// Block = 64 parameters x 4 slices; slice s sums b = s, s + 4, ... with two
-// independent accumulators; the four slice sums are combined in slice order.
-// The order is fixed, so the result is bit-reproducible.
-static __global__ __launch_bounds__(256) void grad_reduce_kernel(const float* __restrict__ part, int nb,
-                                                          int np, float* __restrict__ dtheta) {
+// Block = 64 parameters x 16 slices; slice s sums b = s, s + 16, ... with two
+// independent accumulators; the sixteen slice sums are combined in slice
+// order.  The order is fixed, so the result is bit-reproducible.
+static __global__ __launch_bounds__(1024) void grad_reduce_kernel(const float* __restrict__ part,
+                                                                 int nb, int np,
+                                                                 float* __restrict__ dtheta) {
   const int pl = threadIdx.x & 63, sl = threadIdx.x >> 6;
   const int p = blockIdx.x * 64 + pl;
   double a0 = 0.0, a1 = 0.0;
   if (p < np) {
     int b = sl;
-    for (; b + 4 < nb; b += 8) {
+    for (; b + 16 < nb; b += 32) {
       a0 += part[(size_t)b * np + p];
-      a1 += part[(size_t)(b + 4) * np + p];
+      a1 += part[(size_t)(b + 16) * np + p];
     }
     if (b < nb) a0 += part[(size_t)b * np + p];
   }
-  __shared__ double red[4][64];
+  __shared__ double red[16][64];
   red[sl][pl] = a0 + a1;
   __syncthreads();
-  if (sl == 0 && p < np)
-    dtheta[p] += (float)(((red[0][pl] + red[1][pl]) + red[2][pl]) + red[3][pl]);
+  if (sl == 0 && p < np) {
+    double t = red[0][pl];
+    for (int k = 1; k < 16; ++k) t += red[k][pl];
+    dtheta[p] += (float)t;
+  }
 }
 
 // Launch of nlbm_backward_kernel<L, H, P>, defined in nlbm_bwd.hip.

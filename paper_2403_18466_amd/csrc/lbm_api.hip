@@ -422,7 +422,7 @@ lbm_status launch_bwd(lbm_ctx* ctx, const float* A, const float* theta, const fl
                                  (float)(c.out_scale / c.tau), (int)nitems, nxc);
   if (e != hipSuccess)
     return fail(LBM_ERR_HIP, std::string("launch of nlbm_backward_kernel: ") + hipGetErrorString(e));
-  hipLaunchKernelGGL(grad_reduce_kernel, dim3(blocks_for(nparam, 64)), dim3(256), 0, s, part,
+  hipLaunchKernelGGL(grad_reduce_kernel, dim3(blocks_for(nparam, 64)), dim3(1024), 0, s, part,
                      (int)blocks, nparam, dtheta);
   LBM_LAUNCHED("grad_reduce_kernel");
   return LBM_OK;

@@ -14,8 +14,13 @@ template <class L, int H, int P>
 hipError_t bwd_one(unsigned blocks, hipStream_t s, const float* A, const float* theta,
                    const float* lam1, float* lam0, float* part, Grid G, Force Fc, float rho0,
                    float omega, float knn, int nitems, int nxc) {
-  hipLaunchKernelGGL((nlbm_backward_kernel<L, H, P>), dim3(blocks), dim3(256), 0, s, A, theta,
-                     lam1, lam0, part, G, Fc, rho0, omega, knn, nitems, nxc);
+  if constexpr (CoopLayout<L, H, P>::ok)
+    hipLaunchKernelGGL((nlbm_backward_coop_kernel<L, H, P>), dim3(blocks),
+                       dim3(64 * CoopLayout<L, H, P>::NW), 0, s, A,
+                       theta, lam1, lam0, part, G, Fc, rho0, omega, knn, nitems, nxc);
+  else
+    hipLaunchKernelGGL((nlbm_backward_kernel<L, H, P>), dim3(blocks), dim3(256), 0, s, A, theta,
+                       lam1, lam0, part, G, Fc, rho0, omega, knn, nitems, nxc);
   return hipGetLastError();
 }
 
