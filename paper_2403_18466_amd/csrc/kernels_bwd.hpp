@@ -567,8 +567,15 @@ template <class L, int H, int P>
 struct CoopLayout {
   using S = Shape<L::Q, H>;
   static constexpr int NW = 8;  // wavefronts per workgroup
-  static constexpr int NT2 = S::HB * S::HB, NT1 = S::HB * S::KX, NT3 = S::QB * S::HB;
-  static constexpr int NT = NT2 + NT1 + NT3, TPW = NT / NW;
+  // 16 x 16 gradient tiles: per hidden row block ob the HB tiles of dW2 and
+  // the bias tile of b2; the tiles of dW1 with b1 as input column Q; per
+  // output row block qc the HB tiles of dW3 and the bias tile of b3.  A
+  // bias tile contracts its operand with a ones fragment (every column
+  // holds the sum); like b1, the biases of layers 2 and 3 are thus formed
+  // from the operand-format d2 and dy of the weight gradients.
+  static constexpr int R = S::HB + 1;
+  static constexpr int NT2 = S::HB * R, NT1 = S::HB * S::KX, NT3 = S::QB * R;
+  static constexpr int NT = NT2 + NT1 + NT3, TPW = (NT + NW - 1) / NW;
   // fragments of one group, in slot order
   static constexpr int FDY = 0, FH2 = FDY + S::QB, FD2 = FH2 + S::HB, FH1 = FD2 + S::HB,
                        FD1 = FH1 + S::HB, FX0 = FD1 + S::HB, NFR = FX0 + S::KX;
@@ -580,17 +587,25 @@ struct CoopLayout {
   static constexpr int x_bytes = 64 * XS * 2, d_bytes = 64 * SD * 4, slot_bytes = NFR * 512;
   static constexpr int wave_bytes = x_bytes + d_bytes + slot_bytes;
   static constexpr int bytes = (NFB + NFF) * 512 + H * 4 + NW * wave_bytes;
-  static constexpr bool ok = P != P_F32 && NT % NW == 0 && bytes <= 160 * 1024 &&
-                             (S::n + NW * (H + L::Q)) * 4 <= NW * wave_bytes;
-  // tile t: dW2 (ob, ib) for t < NT2, then dW1|db1 (ob, c), then dW3 (qc, ib)
-  static constexpr int kind(int t) { return t < NT2 ? 2 : (t < NT2 + NT1 ? 1 : 3); }
+  static constexpr bool ok = P != P_F32 && bytes <= 160 * 1024 && S::n * 4 <= NW * wave_bytes;
+  // tile t: kind 2 = dW2, 4 = b2, 1 = dW1|b1, 3 = dW3, 5 = b3; its row and
+  // column block; the slot fragments of its A and B operands (-1: ones)
+  static constexpr int kind(int t) {
+    return t < NT2 ? (t % R < S::HB ? 2 : 4)
+                   : (t < NT2 + NT1 ? 1 : ((t - NT2 - NT1) % R < S::HB ? 3 : 5));
+  }
+  static constexpr int row(int t) {
+    return t < NT2 ? t / R : (t < NT2 + NT1 ? (t - NT2) / S::KX : (t - NT2 - NT1) / R);
+  }
+  static constexpr int col(int t) {
+    return t < NT2 ? t % R : (t < NT2 + NT1 ? (t - NT2) % S::KX : (t - NT2 - NT1) % R);
+  }
   static constexpr int fa(int t) {
-    return t < NT2 ? FD2 + t / S::HB
-                   : (t < NT2 + NT1 ? FD1 + (t - NT2) / S::KX : FDY + (t - NT2 - NT1) / S::HB);
+    return kind(t) == 2 || kind(t) == 4 ? FD2 + row(t) : (kind(t) == 1 ? FD1 : FDY) + row(t);
   }
   static constexpr int fb(int t) {
-    return t < NT2 ? FH1 + t % S::HB
-                   : (t < NT2 + NT1 ? FX0 + (t - NT2) % S::KX : FH2 + (t - NT2 - NT1) % S::HB);
+    return kind(t) == 2 ? FH1 + col(t)
+                        : (kind(t) == 1 ? FX0 + col(t) : (kind(t) == 3 ? FH2 + col(t) : -1));
   }
 };
 
@@ -630,16 +645,20 @@ __device__ inline void load_forward_weights(typename Frag<P>::T* w, const float*
 template <class CL, int P, int W>
 __device__ inline void coop_tiles(f4 (&acc)[CL::TPW], const unsigned char* slots, int rdo) {
   using Fr = typename Frag<P>::T;
+  constexpr unsigned one2 = P == P_BF16 ? 0x3F803F80u : 0x3C003C00u;  // two 16-bit 1.0
+  const Fr ones = {one2, one2};
   auto frag = [&](int w, int f) {
-    return *reinterpret_cast<const Fr*>(slots + w * CL::wave_bytes + f * 512 + rdo);
+    return f < 0 ? ones : *reinterpret_cast<const Fr*>(slots + w * CL::wave_bytes + f * 512 + rdo);
   };
 #pragma unroll
   for (int j = 0; j < CL::TPW; ++j) {
     const int t = W * CL::TPW + j;
+    if (t < CL::NT) {
 #pragma unroll
-    for (int p = 0; p < CL::NW; p += 2)
-      acc[j] = mma_pair<P>(acc[j], frag(p, CL::fa(t)), frag(p + 1, CL::fa(t)),
-                           frag(p, CL::fb(t)), frag(p + 1, CL::fb(t)));
+      for (int p = 0; p < CL::NW; p += 2)
+        acc[j] = mma_pair<P>(acc[j], frag(p, CL::fa(t)), frag(p + 1, CL::fa(t)),
+                             frag(p, CL::fb(t)), frag(p + 1, CL::fb(t)));
+    }
   }
 }
 
@@ -651,20 +670,20 @@ __device__ inline void coop_put(const f4 (&acc)[CL::TPW], float* red, int lg, in
 #pragma unroll
   for (int j = 0; j < CL::TPW; ++j) {
     const int t = W * CL::TPW + j;
+    if (t >= CL::NT) continue;
+    const int a = 16 * CL::row(t) + 4 * lg, b = 16 * CL::col(t) + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const float v = acc[j][r];
-      if (CL::kind(t) == 2) {
-        const int o = 16 * (t / S::HB) + 4 * lg + r, i = 16 * (t % S::HB) + li;
-        red[S::oW2 + o * S::H + i] = v;
-      } else if (CL::kind(t) == 1) {
-        const int u = t - CL::NT2, o = 16 * (u / S::KX) + 4 * lg + r, k = 16 * (u % S::KX) + li;
-        if (k < S::Q) red[S::oW1 + o * S::Q + k] = v;
-        else if (k == S::Q) red[S::ob1 + o] = v;
-      } else {
-        const int u = t - CL::NT2 - CL::NT1, q = 16 * (u / S::HB) + 4 * lg + r,
-                  i = 16 * (u % S::HB) + li;
-        if (q < S::Q) red[S::oW3 + q * S::H + i] = v;
+      switch (CL::kind(t)) {
+        case 2: red[S::oW2 + (a + r) * S::H + b] = v; break;
+        case 4: if (li == 0) red[S::ob2 + a + r] = v; break;
+        case 1:
+          if (b < S::Q) red[S::oW1 + (a + r) * S::Q + b] = v;
+          else if (b == S::Q) red[S::ob1 + a + r] = v;
+          break;
+        case 3: if (a + r < S::Q) red[S::oW3 + (a + r) * S::H + b] = v; break;
+        default: if (li == 0 && a + r < S::Q) red[S::ob3 + a + r] = v; break;
       }
     }
   }
@@ -739,14 +758,9 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   const int per = (nitems + nb - 1) / nb;
   const int ib0 = min(lb * per, nitems), ib1 = min(ib0 + per, nitems);
 
-  f4 acc[CL::TPW], db2[S::HB];
+  f4 acc[CL::TPW];
 #pragma unroll
   for (int j = 0; j < CL::TPW; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int a = 0; a < S::HB; ++a) db2[a] = f4{0.f, 0.f, 0.f, 0.f};
-  float db3[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) db3[q] = 0.f;
 
   const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * Q) * 4u;
   const rsrc_t rA = make_rsrc(A, bytes), rL1 = make_rsrc(lam1, bytes),
@@ -796,13 +810,13 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int q = 4 * c + r;
-        float d = q < Q ? knn * nu[q] : 0.f;
-        v[r] = d;
-        if (q < Q) db3[q] += d;
+        v[r] = q < Q ? knn * nu[q] : 0.f;
       }
       *reinterpret_cast<f4*>(D + lane * CL::SD + 4 * c) = v;
     }
     wave_lds_sync();
+    // the next item's loads are in flight while this item's network runs
+    if (k + NW < ib1) load(it + NW, gc, mc);
 
     auto put_t = [&](int f, Fr v) {
 #pragma unroll
@@ -884,9 +898,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
         Fr d2f[S::HB], d1f[S::HB];
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob) {
-          const f4 d2 = a2[ob] * (1.f - t2[ob] * t2[ob]);
-          db2[ob] += d2;
-          d2f[ob] = to_frag<P>(d2);
+          d2f[ob] = to_frag<P>(a2[ob] * (1.f - t2[ob] * t2[ob]));
           put_t(CL::FD2 + ob, d2f[ob]);
         }
         f4 a3[S::HB];
@@ -915,8 +927,6 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
       // this wavefront's weight-gradient tiles over the nodes of the step
       coop_tiles_of<CL, P>(wave, acc, slots, rdo);
     }
-    // the next item's loads go out before this item's results
-    if (k + NW < ib1) load(it + NW, gc, mc);
     wave_lds_sync();
 #pragma unroll
     for (int q = 0; q < Q; ++q) lam[q] += D[lane * CL::SD + q];
@@ -925,41 +935,10 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   }
 
   // Partial gradient of the workgroup: the tiles are disjoint between the
-  // wavefronts.  The bias sums of layers 2 and 3 are reduced within every
-  // wavefront at once, then added over the wavefronts in wave order.
+  // wavefronts and cover every parameter.
   __syncthreads();
   float* red = reinterpret_cast<float*>(wl);
-  float* bsum = red + S::n;  // [NW][H + Q]
   coop_put_of<CL>(wave, acc, red, lg, li);
-#pragma unroll
-  for (int ob = 0; ob < S::HB; ++ob)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      float sb = db2[ob][r];
-      sb += __shfl_xor(sb, 8);
-      sb += __shfl_xor(sb, 4);
-      sb += __shfl_xor(sb, 2);
-      sb += __shfl_xor(sb, 1);
-      if (li == 0) bsum[wave * (H + Q) + 16 * ob + 4 * lg + r] = sb;
-    }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    float sq = db3[q];
-    sq += __shfl_xor(sq, 32);
-    sq += __shfl_xor(sq, 16);
-    sq += __shfl_xor(sq, 8);
-    sq += __shfl_xor(sq, 4);
-    sq += __shfl_xor(sq, 2);
-    sq += __shfl_xor(sq, 1);
-    if (lane == 0) bsum[wave * (H + Q) + H + q] = sq;
-  }
-  __syncthreads();
-  if (threadIdx.x < H + Q) {
-    const int i = threadIdx.x;
-    float sum = bsum[i];
-    for (int w = 1; w < NW; ++w) sum += bsum[w * (H + Q) + i];
-    red[i < H ? S::ob2 + i : S::ob3 + (i - H)] = sum;
-  }
   __syncthreads();
   float* pb = part + (size_t)blockIdx.x * S::n;
   for (int i = threadIdx.x; i < S::n; i += blockDim.x) pb[i] = red[i];
