@@ -497,16 +497,16 @@ struct StepLds {
   // (row 4 ob + g holds b3[16 ob + 4 g .. + 3]), not in registers
   static constexpr int B3 = YC + YQ;
   // wavefronts per SIMD the compiler must leave room for: three for the
-  // unforced 16-bit D3Q19 instance, else no constraint
+  // unforced 16-bit D3Q19 instances, else no constraint
   static constexpr int min_waves(int prec, bool forced) {
-    return (L::Q == 19 && prec == P_BF16 && !forced) ? 3 : 1;
+    return (L::Q == 19 && prec != P_F32 && !forced) ? 3 : 1;
   }
 };
 
 // FORCED: the body force of eq. fext is applied (Force::kind != 0).  The
 // unforced instances leave out the force's registers (its float64 sine and
-// 64-bit argument reduction): 116 instead of 150 registers per lane for the
-// 16-bit D2Q9 instance, 176 instead of 233 for D3Q19.
+// 64-bit argument reduction): 108 instead of 149 registers per lane for the
+// 16-bit D2Q9 instance, 158 instead of 216 for D3Q19.
 template <class L, int H, int P, bool FORCED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     StepLds<L, H>::min_waves(P, FORCED)))) void nlbm_step_kernel(const float* __restrict__ Ain,
@@ -518,7 +518,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   using LD = StepLds<L, H>;
   using F = typename Frag<P>::T;
   constexpr int Q = L::Q;
-  __shared__ float lds[4 * LD::per_wave];
+  __shared__ __attribute__((aligned(16))) float lds[4 * LD::per_wave];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, lg = lane >> 4, li = lane & 15;
   float* X = lds + wave * LD::per_wave;
@@ -529,10 +529,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   const int nw = nb * 4, wv = lb * 4 + wave;
   const int per = (nitems + nw - 1) / nw;
   const int it0 = wv * per, it1 = min(it0 + per, nitems);
-  if (it0 >= it1) return;
 
+  // The weight fragments reach the registers through the (still unused)
+  // tile memory: the workgroup stages them from coalesced reads of theta,
+  // then every wave loads its copy with lane-contiguous reads.
   Weights<P, S> W;
-  W.load(theta);
+  {
+    using F = typename Frag<P>::T;
+    constexpr int NF = S::HB * S::KX + S::HB * S::HB + S::QB * S::HB;
+    static_assert(NF * 64 * (int)sizeof(F) <= 4 * LD::per_wave * 4, "fragment staging");
+    F* fr = reinterpret_cast<F*>(lds);
+    stage_weight_fragments<P, S>(fr, theta);
+    W.load_staged(fr, theta);
+    __syncthreads();
+  }
+  if (it0 >= it1) return;
 
   const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * Q) * 4u;
   const rsrc_t src = make_rsrc(Ain, bytes), dst = make_rsrc(Aout, bytes);

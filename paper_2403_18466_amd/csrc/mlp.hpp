@@ -215,6 +215,33 @@ struct Weights {
   f4 b2[S::HB];
   f4 b3[S::QB];
 
+  // from the fragments staged in LDS (stage_weight_fragments), with b2 and
+  // b3 read from theta
+  __device__ inline void load_staged(const F* fr, const float* __restrict__ th) {
+    const int l = threadIdx.x & 63, g = l >> 4;
+    constexpr float sc = tanh_weight_scale<P>();
+    constexpr int N1 = S::HB * S::KX, N2 = S::HB * S::HB;
+#pragma unroll
+    for (int ob = 0; ob < S::HB; ++ob) {
+#pragma unroll
+      for (int c = 0; c < S::KX; ++c) w1[ob][c] = fr[64 * (ob * S::KX + c) + l];
+#pragma unroll
+      for (int c = 0; c < S::HB; ++c) w2[ob][c] = fr[64 * (N1 + ob * S::HB + c) + l];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) b2[ob][r] = sc * th[S::ob2 + 16 * ob + 4 * g + r];
+    }
+#pragma unroll
+    for (int ob = 0; ob < S::QB; ++ob) {
+#pragma unroll
+      for (int c = 0; c < S::HB; ++c) w3[ob][c] = fr[64 * (N1 + N2 + ob * S::HB + c) + l];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int q = 16 * ob + 4 * g + r;
+        b3[ob][r] = q < S::Q ? th[S::ob3 + q] : 0.f;
+      }
+    }
+  }
+
   // lane-local A-operand entry: row o, k = 16 c + 4 g + r
   __device__ inline void load(const float* __restrict__ th) {
     const int l = threadIdx.x & 63, g = l >> 4, i = l & 15;
@@ -261,5 +288,48 @@ struct Weights {
     }
   }
 };
+
+// Block-cooperative staging of the fragments Weights::load builds, into a
+// fragment-major LDS array fr (fragment f of lane l at fr[64 f + l]): W1
+// with b1 as input column Q (HB x KX fragments), W2 (HB x HB), W3 (QB x HB),
+// the two tanh layers scaled.  theta is read once per workgroup with
+// consecutive threads on consecutive parameters, and every value is stored
+// at its fragment position; the padding entries are zero.  Ends with a
+// workgroup barrier.
+template <int P, class S>
+__device__ inline void stage_weight_fragments(typename Frag<P>::T* fr,
+                                              const float* __restrict__ th) {
+  using F = typename Frag<P>::T;
+  constexpr int N1 = S::HB * S::KX, N2 = S::HB * S::HB, N3 = S::QB * S::HB;
+  constexpr int NF = N1 + N2 + N3;
+  constexpr float sc = tanh_weight_scale<P>();
+  const int nt = blockDim.x, tid = threadIdx.x;
+  for (int e = tid; e < NF * 64; e += nt) fr[e] = F{};
+  __syncthreads();
+  // element r of fragment f, lane l; l = row % 16 + 16 ((k % 16) / 4), r = k % 4
+  auto put = [&](int f, int row, int k, float v) {
+    const int e = 64 * f + (row & 15) + 16 * ((k & 15) >> 2);
+    if constexpr (P == P_F32) {
+      reinterpret_cast<float*>(fr)[4 * e + (k & 3)] = v;
+    } else {
+      const unsigned w = pack2<P>(v, 0.f);
+      reinterpret_cast<unsigned short*>(fr)[4 * e + (k & 3)] = (unsigned short)w;
+    }
+  };
+  for (int j = tid; j < S::H * S::Q; j += nt) {
+    const int o = j / S::Q, k = j - o * S::Q;
+    put((o >> 4) * S::KX + (k >> 4), o, k, sc * th[S::oW1 + j]);
+  }
+  for (int o = tid; o < S::H; o += nt) put((o >> 4) * S::KX + (S::Q >> 4), o, S::Q, sc * th[S::ob1 + o]);
+  for (int j = tid; j < S::H * S::H; j += nt) {
+    const int o = j / S::H, k = j - o * S::H;
+    put(N1 + (o >> 4) * S::HB + (k >> 4), o, k, sc * th[S::oW2 + j]);
+  }
+  for (int j = tid; j < S::Q * S::H; j += nt) {
+    const int q = j / S::H, k = j - q * S::H;
+    put(N1 + N2 + (q >> 4) * S::HB + (k >> 4), q, k, th[S::oW3 + j]);
+  }
+  __syncthreads();
+}
 
 }  // namespace lbm
