@@ -228,39 +228,44 @@ __global__ void shift_kernel(const float* __restrict__ src, float* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Moments and float64 diagnostics.  Grid (MOM_BLOCKS, batch) x 256 threads;
-// each block writes {mass, kinetic energy, non-finite count} partials, summed
-// in a fixed order by diag_reduce_kernel.
+// Moments and float64 diagnostics.  Grid (MOMENT_BLOCKS, batch) x 256
+// threads; a block walks 256-node row chunks of its field (one node per
+// thread, buffer loads as in the step kernels) and writes {mass, kinetic
+// energy, non-finite count} partials, summed in a fixed order by
+// diag_reduce_kernel.
 // ---------------------------------------------------------------------------
-constexpr int MOM_BLOCKS = 512;
+constexpr int MOM_BLOCKS = 512;       // loss reductions
+constexpr int MOMENT_BLOCKS = 4096;   // moments, per field
 
 template <class L>
 __global__ __launch_bounds__(256) void moments_kernel(const float* __restrict__ A,
                                                       float* __restrict__ rho,
                                                       float* __restrict__ u,
                                                       double* __restrict__ partial, Grid G,
-                                                      float rho0, Force Fc) {
+                                                      float rho0, Force Fc, int nxc) {
   const int b = blockIdx.y;
+  const int per_field = nxc * G.ny * G.nz;
+  const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * L::Q) * 4u;
+  const rsrc_t src = make_rsrc(A, bytes);
   double mass = 0.0, ke = 0.0, bad = 0.0;
-  for (long long node = blockIdx.x * 256LL + threadIdx.x; node < G.plane;
-       node += (long long)gridDim.x * 256) {
-    int x, y, z, bb;
-    decode(G, node, x, y, z, bb);
+  for (int k = blockIdx.x; k < per_field; k += gridDim.x) {
+    const Item t = locate_item(b * per_field + k, nxc, G, threadIdx.x, 256);
+    if (!t.active) continue;
     float g[L::Q];
-    gather<L>(A, G, b, x, y, z, g);
+    gather_item<L>(src, G, t, g);
     bool finite = true;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) finite = finite && __builtin_isfinite(g[q]);
     float drho, j[3], F[3];
     moments<L>(g, drho, j);
-    body_force(Fc, G, x, y, z, F);
+    body_force(Fc, G, t.x, t.y, t.z, F);
     float r = rho0 + drho;
     float inv = 1.f / r;
     float uv[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) uv[a] = (j[a] + 0.5f * F[a]) * inv;
-    long long pn = (long long)b * G.plane + node;
-    if (rho) rho[pn] = r;
+    const long long node = ((long long)t.z * G.ny + t.y) * G.nx + t.x;
+    if (rho) rho[(long long)b * G.plane + node] = r;
     if (u) {
 #pragma unroll
       for (int a = 0; a < L::D; ++a) u[((long long)b * L::D + a) * G.plane + node] = uv[a];

@@ -26,7 +26,7 @@ struct lbm_ctx {
   lbm_config cfg;
   int device;
   int ncu;
-  double* partial;  // float64 reduction partials, [batch][MOM_BLOCKS][3]
+  double* partial;  // float64 reduction partials, [batch][max(MOM_BLOCKS, MOMENT_BLOCKS)][3]
   // LBM_NET_LEAKY_300_300_100: theta -> fragment-order gather table and the
   // packed weights it fills
   int* wide_idx;
@@ -271,12 +271,13 @@ template <class L>
 lbm_status run_moments(lbm_ctx* ctx, const float* A, float* rho, float* u, double* diag,
                        hipStream_t s) {
   Grid G = grid_of(ctx->cfg);
-  hipLaunchKernelGGL(moments_kernel<L>, dim3(MOM_BLOCKS, G.batch), dim3(256), 0, s, A, rho, u,
-                     ctx->partial, G, (float)ctx->cfg.rho0, force_of(ctx->cfg));
+  const int nxc = (G.nx + 255) / 256;
+  hipLaunchKernelGGL(moments_kernel<L>, dim3(MOMENT_BLOCKS, G.batch), dim3(256), 0, s, A, rho, u,
+                     ctx->partial, G, (float)ctx->cfg.rho0, force_of(ctx->cfg), nxc);
   LBM_LAUNCHED("moments_kernel");
   if (diag) {
     hipLaunchKernelGGL(diag_reduce_kernel, dim3(G.batch), dim3(256), 0, s, ctx->partial, diag,
-                       MOM_BLOCKS);
+                       MOMENT_BLOCKS);
     LBM_LAUNCHED("diag_reduce_kernel");
   }
   return LBM_OK;
@@ -510,7 +511,8 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   ctx->wide_bpacked = nullptr;
   ctx->diag = nullptr;
   ctx->diag_bytes = 0;
-  size_t bytes = sizeof(double) * 3 * MOM_BLOCKS * (size_t)cfg->batch;
+  size_t bytes = sizeof(double) * 3 * (size_t)(MOM_BLOCKS > MOMENT_BLOCKS ? MOM_BLOCKS : MOMENT_BLOCKS) *
+                 (size_t)cfg->batch;
   hipError_t e = hipMalloc(&ctx->partial, bytes);
   if (e != hipSuccess) {
     delete ctx;
