@@ -613,31 +613,87 @@ struct CoopLayout {
 // holds one partial gradient vector per workgroup.
 constexpr unsigned bwd_blocks(int ncu) { return (unsigned)ncu; }
 
-// Forward weight fragments in LDS, fragment-major: W1 (ob, c) at ob KX + c
-// with the layer-1 bias as input column Q, then W2 (ob, c) at
-// HB KX + ob HB + c; both scaled by the tanh argument scale.
-template <class L, int H, int P>
-__device__ inline void load_forward_weights(typename Frag<P>::T* w, const float* __restrict__ th) {
+// All weights of the cooperative kernel in LDS, from one pass over theta by
+// the NT threads of the workgroup (consecutive threads on consecutive
+// parameters, every read issued before any is used).  Each value goes to its
+// positions in the fragment-major arrays: bwd = W3^T (HB x QB fragments),
+// W2^T (HB x HB), W1^T (KX x HB), as load_transposed_weights builds them;
+// fwd = W1 with b1 as input column Q (HB x KX), then W2 (HB x HB), scaled
+// like the forward's; b2s = c b2.  Padding entries are zero.
+// Ends with a workgroup barrier.
+template <class L, int H, int P, int NT>
+__device__ inline void stage_adjoint_weights(typename Frag<P>::T* bwd, typename Frag<P>::T* fwd,
+                                             float* b2s, const float* __restrict__ th) {
   using S = Shape<L::Q, H>;
+  using F = typename Frag<P>::T;
+  constexpr int Q = L::Q;
+  constexpr int NF3 = S::HB * S::QB, NF2 = S::HB * S::HB, NFB = NF3 + NF2 + S::KX * S::HB;
   constexpr int N1 = S::HB * S::KX, NFF = N1 + S::HB * S::HB;
   constexpr float sc = tanh_weight_scale<P>();
-  for (int e = threadIdx.x; e < NFF * 64; e += blockDim.x) {
-    const int f = e >> 6, l = e & 63, g = l >> 4, i = l & 15;
-    f4 v;
-    if (f < N1) {
-      const int o = 16 * (f / S::KX) + i, c = f % S::KX;
+  constexpr int C1 = (H * Q + NT - 1) / NT, CB = (H + NT - 1) / NT, C2 = (H * H + NT - 1) / NT,
+                C3 = (Q * H + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  float v1[C1], vb[CB], vb2[CB], v2[C2], v3[C3];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int k = 16 * c + 4 * g + r;
-        v[r] = sc * (k < S::Q ? th[S::oW1 + o * S::Q + k] : (k == S::Q ? th[S::ob1 + o] : 0.f));
-      }
-    } else {
-      const int ff = f - N1, o = 16 * (ff / S::HB) + i, c = ff % S::HB;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = sc * th[S::oW2 + o * S::H + 16 * c + 4 * g + r];
-    }
-    w[e] = to_frag<P>(v);
+  for (int i = 0; i < C1; ++i) {
+    const int j = tid + i * NT;
+    v1[i] = j < H * Q ? th[S::oW1 + j] : 0.f;
   }
+#pragma unroll
+  for (int i = 0; i < CB; ++i) {
+    const int j = tid + i * NT;
+    vb[i] = j < H ? th[S::ob1 + j] : 0.f;
+    vb2[i] = j < H ? th[S::ob2 + j] : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < C2; ++i) {
+    const int j = tid + i * NT;
+    v2[i] = j < H * H ? th[S::oW2 + j] : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < C3; ++i) {
+    const int j = tid + i * NT;
+    v3[i] = j < Q * H ? th[S::oW3 + j] : 0.f;
+  }
+  for (int e = tid; e < NFB * 64; e += NT) bwd[e] = F{};
+  for (int e = tid; e < NFF * 64; e += NT) fwd[e] = F{};
+  __syncthreads();
+  // element r of fragment f, lane l = row % 16 + 16 ((k % 16) / 4), r = k % 4
+  auto put = [&](F* fr, int f, int row, int k, float v) {
+    const int e = 64 * f + (row & 15) + 16 * ((k & 15) >> 2);
+    const unsigned w = pack2<P>(v, 0.f);
+    reinterpret_cast<unsigned short*>(fr)[4 * e + (k & 3)] = (unsigned short)w;
+  };
+#pragma unroll
+  for (int i = 0; i < C1; ++i) {
+    const int j = tid + i * NT, o = j / Q, k = j - o * Q;
+    if (j < H * Q) {
+      put(fwd, (o >> 4) * S::KX + (k >> 4), o, k, sc * v1[i]);             // W1 (o, k)
+      put(bwd, NF3 + NF2 + (k >> 4) * S::HB + (o >> 4), k, o, sc * v1[i]);  // W1^T (k, o)
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < CB; ++i) {
+    const int o = tid + i * NT;
+    if (o < H) {
+      put(fwd, (o >> 4) * S::KX + (Q >> 4), o, Q, sc * vb[i]);
+      b2s[o] = sc * vb2[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < C2; ++i) {
+    const int j = tid + i * NT, o = j / H, k = j - o * H;
+    if (j < H * H) {
+      put(fwd, N1 + (o >> 4) * S::HB + (k >> 4), o, k, sc * v2[i]);   // W2 (o, k)
+      put(bwd, NF3 + (k >> 4) * S::HB + (o >> 4), k, o, sc * v2[i]);  // W2^T (k, o)
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < C3; ++i) {
+    const int j = tid + i * NT, q = j / H, h = j - q * H;
+    if (j < Q * H) put(bwd, (h >> 4) * S::QB + (q >> 4), h, q, v3[i]);  // W3^T (h, q)
+  }
+  __syncthreads();
 }
 
 // acc[j] += the product of tile W TPW + j over the slots (the nodes of
@@ -729,10 +785,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
   constexpr float sc = tanh_weight_scale<P>();
-  load_transposed_weights<L, H, P>(wts, theta);
-  load_forward_weights<L, H, P>(wts + CL::NFB * 64, theta);
-  for (int o = threadIdx.x; o < H; o += blockDim.x) b2s[o] = sc * theta[S::ob2 + o];
-  __syncthreads();
+  stage_adjoint_weights<L, H, P, 64 * NW>(wts, wts + CL::NFB * 64, b2s, theta);
   const Fr* W3T = wts;
   const Fr* W2T = wts + S::HB * S::QB * 64;
   const Fr* W1T = wts + (S::HB * S::QB + S::HB * S::HB) * 64;

@@ -544,7 +544,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     constexpr int NF = S::HB * S::KX + S::HB * S::HB + S::QB * S::HB;
     static_assert(NF * 64 * (int)sizeof(F) <= 4 * LD::per_wave * 4, "fragment staging");
     F* fr = reinterpret_cast<F*>(lds);
-    stage_weight_fragments<P, S>(fr, theta);
+    stage_weight_fragments<P, S, 256>(fr, theta);
     W.load_staged(fr, theta);
     __syncthreads();
   }

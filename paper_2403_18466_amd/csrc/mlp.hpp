@@ -292,19 +292,42 @@ struct Weights {
 // Block-cooperative staging of the fragments Weights::load builds, into a
 // fragment-major LDS array fr (fragment f of lane l at fr[64 f + l]): W1
 // with b1 as input column Q (HB x KX fragments), W2 (HB x HB), W3 (QB x HB),
-// the two tanh layers scaled.  theta is read once per workgroup with
-// consecutive threads on consecutive parameters, and every value is stored
-// at its fragment position; the padding entries are zero.  Ends with a
-// workgroup barrier.
-template <int P, class S>
+// the two tanh layers scaled.  The NT threads of the workgroup read theta
+// once, consecutive threads on consecutive parameters, all reads issued
+// before any is used; every value is then stored at its fragment position.
+// The padding entries are zero.  Ends with a workgroup barrier.
+template <int P, class S, int NT>
 __device__ inline void stage_weight_fragments(typename Frag<P>::T* fr,
                                               const float* __restrict__ th) {
   using F = typename Frag<P>::T;
   constexpr int N1 = S::HB * S::KX, N2 = S::HB * S::HB, N3 = S::QB * S::HB;
   constexpr int NF = N1 + N2 + N3;
   constexpr float sc = tanh_weight_scale<P>();
-  const int nt = blockDim.x, tid = threadIdx.x;
-  for (int e = tid; e < NF * 64; e += nt) fr[e] = F{};
+  constexpr int C1 = (S::H * S::Q + NT - 1) / NT, CB = (S::H + NT - 1) / NT,
+                C2 = (S::H * S::H + NT - 1) / NT, C3 = (S::Q * S::H + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  float v1[C1], vb[CB], v2[C2], v3[C3];
+#pragma unroll
+  for (int i = 0; i < C1; ++i) {
+    const int j = tid + i * NT;
+    v1[i] = j < S::H * S::Q ? th[S::oW1 + j] : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < CB; ++i) {
+    const int j = tid + i * NT;
+    vb[i] = j < S::H ? th[S::ob1 + j] : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < C2; ++i) {
+    const int j = tid + i * NT;
+    v2[i] = j < S::H * S::H ? th[S::oW2 + j] : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < C3; ++i) {
+    const int j = tid + i * NT;
+    v3[i] = j < S::Q * S::H ? th[S::oW3 + j] : 0.f;
+  }
+  for (int e = tid; e < NF * 64; e += NT) fr[e] = F{};
   __syncthreads();
   // element r of fragment f, lane l; l = row % 16 + 16 ((k % 16) / 4), r = k % 4
   auto put = [&](int f, int row, int k, float v) {
@@ -316,18 +339,25 @@ __device__ inline void stage_weight_fragments(typename Frag<P>::T* fr,
       reinterpret_cast<unsigned short*>(fr)[4 * e + (k & 3)] = (unsigned short)w;
     }
   };
-  for (int j = tid; j < S::H * S::Q; j += nt) {
-    const int o = j / S::Q, k = j - o * S::Q;
-    put((o >> 4) * S::KX + (k >> 4), o, k, sc * th[S::oW1 + j]);
+#pragma unroll
+  for (int i = 0; i < C1; ++i) {
+    const int j = tid + i * NT, o = j / S::Q, k = j - o * S::Q;
+    if (j < S::H * S::Q) put((o >> 4) * S::KX + (k >> 4), o, k, sc * v1[i]);
   }
-  for (int o = tid; o < S::H; o += nt) put((o >> 4) * S::KX + (S::Q >> 4), o, S::Q, sc * th[S::ob1 + o]);
-  for (int j = tid; j < S::H * S::H; j += nt) {
-    const int o = j / S::H, k = j - o * S::H;
-    put(N1 + (o >> 4) * S::HB + (k >> 4), o, k, sc * th[S::oW2 + j]);
+#pragma unroll
+  for (int i = 0; i < CB; ++i) {
+    const int o = tid + i * NT;
+    if (o < S::H) put((o >> 4) * S::KX + (S::Q >> 4), o, S::Q, sc * vb[i]);
   }
-  for (int j = tid; j < S::Q * S::H; j += nt) {
-    const int q = j / S::H, k = j - q * S::H;
-    put(N1 + N2 + (q >> 4) * S::HB + (k >> 4), q, k, th[S::oW3 + j]);
+#pragma unroll
+  for (int i = 0; i < C2; ++i) {
+    const int j = tid + i * NT, o = j / S::H, k = j - o * S::H;
+    if (j < S::H * S::H) put(N1 + (o >> 4) * S::HB + (k >> 4), o, k, sc * v2[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < C3; ++i) {
+    const int j = tid + i * NT, q = j / S::H, k = j - q * S::H;
+    if (j < S::Q * S::H) put(N1 + N2 + (q >> 4) * S::HB + (k >> 4), q, k, v3[i]);
   }
   __syncthreads();
 }
