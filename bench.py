@@ -544,7 +544,8 @@ def main():
                               "bf16_over_fp32_step_time": tr["fp32"]["train_step_ms"] /
                               tr["bf16"]["train_step_ms"],
                               "adjoint_roofline": {
-                                  "kernel": "nlbm_backward_kernel<D2Q9, 64, bf16>",
+                                  "kernel": "nlbm_backward_coop_kernel<D2Q9, 64, bf16> + "
+                                            "grad_reduce_kernel",
                                   "bound": "alu", "achieved": lups / 1e9,
                                   "peak": ADJ_ACT_PEAK_LUPS / 1e9,
                                   "unit": "GLUP/s (activation ALU ceiling of the adjoint: the "
