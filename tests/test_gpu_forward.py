@@ -63,6 +63,23 @@ def test_init_and_moments(lbm, lat, shape):
     assert (d[:, 2] == 0).all()
 
 
+def test_moments_blocks_walk_several_chunks(lbm):
+    """More 256-node row chunks per field than moments workgroups (2 chunks
+    per row, the second ragged, 4200 chunks), two fields: every workgroup
+    walks more than one chunk."""
+    ocfg = oracle.Config(nx=300, ny=2100, batch=2)
+    g = random_state(ocfg, 5, scale=0.03)
+    L = lbm.Lattice(lib_config(ocfg))
+    r2, u2, diag = L.moments(dev(to_shifted(g, "D2Q9")))
+    orho, ou, odiag = oracle.moments(ocfg, g)
+    assert np.abs(host(r2) - orho).max() < 1e-6
+    assert np.abs(host(u2) - ou).max() < 1e-5
+    d = host(diag)
+    assert np.abs(d[:, 0] - odiag[:, 0]).max() < 1e-6 * odiag[:, 0].max()
+    assert np.abs(d[:, 1] - odiag[:, 1]).max() < 1e-5 * odiag[:, 1].max()
+    assert (d[:, 2] == 0).all()
+
+
 def test_moments_count_nonfinite(lbm):
     ocfg = oracle.Config(nx=16, ny=8, batch=2)
     g = random_state(ocfg, 3)

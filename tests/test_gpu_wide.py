@@ -247,6 +247,28 @@ def test_wide_adjoint_reduced_precision(lbm, prec):
     assert e_th < (2e-2 if prec == "bf16" else 3e-3)
 
 
+def test_wide_adjoint_4335_nodes(lbm):
+    """bf16 adjoint on 4335 nodes (68 node tiles of 64 in the products, the
+    last one ragged) against the oracle's emulated-rounding adjoint, every
+    parameter block on its own."""
+    ocfg = oracle.Config(lattice="D3Q19", nx=17, ny=17, nz=15, batch=1, tau=0.51, hidden=300,
+                         net="paper", out_scale=0.25, quant="bf16")
+    theta = inputs.glorot_params_net(inputs.net_widths(19, 0, "paper"), seed=1)
+    g = random_state(ocfg, 57, scale=0.03)
+    lam1 = random_state(ocfg, 58, scale=1.0)
+    want, wdth = oracle.step_adjoint(ocfg, g, lam1, theta.astype(np.float64))
+    got, gdth = gpu_adjoint(lbm, ocfg, g, lam1, theta, prec="bf16")
+    e_lam, e_th = rel_l2(got, want), rel_l2(gdth, wdth)
+    offs = _blocks(ocfg.Q)
+    errs = [rel_l2(gdth[a:b], wdth[a:b]) for a, b in zip(offs[:-1], offs[1:])]
+    print(f"4335 nodes: lam rel L2 {e_lam:.2e}, dtheta rel L2 {e_th:.2e}, blocks " +
+          " ".join(f"{e:.1e}" for e in errs))
+    assert e_lam < 2e-3
+    assert e_th < 2e-2
+    for e in errs:
+        assert e < 5e-2
+
+
 def test_wide_unrolled_gradient(lbm):
     """6 unrolled steps of the SI's network on D3Q19 (forced), fp32, the
     population loss on a node subset: the parameter gradient against the
