@@ -560,8 +560,10 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
 // Slot fragment layout: fragment f holds, for logical lane l = i + 16 g,
 // the four 16-bit values A[i][4 g + r] (feature i of the fragment's 16,
 // nodes 4 g + r of the group) at byte 512 f + 8 swz(l) + 2 r, with
-// swz(l) = l ^ ((l >> 4) & 3).  The swizzle spreads the transposing 16-bit
-// writes (one feature row at a time from the D layout) over all 32 banks.
+// swz(l) = l ^ ((l >> 4) & 3).  The transposing writes from the D layout
+// store two nodes per dword (neighbouring lanes exchange half of their
+// values first); the swizzle puts exactly two lanes of each such write on
+// every bank.
 // ---------------------------------------------------------------------------
 template <class L, int H, int P>
 struct CoopLayout {
@@ -801,9 +803,16 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   // contraction-layout addresses: this lane's read offset, and the write
   // offsets of its four D-layout values (feature 4 lg + r, node li)
   const int rdo = 8 * (lane ^ ((lane >> 4) & 3));
-  int wro[4];
+  // A transposed fragment is written two nodes per dword: lanes li and
+  // li ^ 1 swap half of their four values, the even lane then holds
+  // features 0 and 1 of both nodes, the odd lane features 2 and 3.
+  const bool odd = li & 1;
+  int wro[2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) wro[r] = 8 * (4 * lg + (r ^ (li >> 2)) + 16 * (li >> 2)) + 2 * (li & 3);
+  for (int j = 0; j < 2; ++j) {
+    const int r = 2 * (li & 1) + j;
+    wro[j] = 8 * (4 * lg + (r ^ (li >> 2)) + 16 * (li >> 2)) + 4 * ((li & 3) >> 1);
+  }
 
   // workgroup range of items; wavefront w takes item k + w of each step
   const int nb = gridDim.x, bid = blockIdx.x;
@@ -872,10 +881,12 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
     if (k + NW < ib1) load(it + NW, gc, mc);
 
     auto put_t = [&](int f, Fr v) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        *reinterpret_cast<unsigned short*>(slot + f * 512 + wro[r]) =
-            (unsigned short)(v[r >> 1] >> (16 * (r & 1)));
+      const unsigned send = odd ? v[0] : v[1];
+      // quad permutation [1, 0, 3, 2]: every lane receives its neighbour's value
+      const unsigned recv = (unsigned)__builtin_amdgcn_mov_dpp((int)send, 0xB1, 0xF, 0xF, false);
+      const unsigned lo = odd ? recv : v[0], hi = odd ? v[1] : recv;  // even node, odd node
+      *reinterpret_cast<unsigned*>(slot + f * 512 + wro[0]) = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+      *reinterpret_cast<unsigned*>(slot + f * 512 + wro[1]) = __builtin_amdgcn_perm(hi, lo, 0x07060302u);
     };
 #pragma unroll 1
     for (int jg = 0; jg < 4; ++jg) {
@@ -885,17 +896,12 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
       // overlaps it (the scheduling barriers keep the reads there).
       f4 t1[S::HB], t2[S::HB];
       {
-        Fr xin[S::KX], x0T[S::KX], w1[S::HB * S::KX], h1[S::HB], h2[S::HB];
+        Fr xin[S::KX], w1[S::HB * S::KX], h1[S::HB], h2[S::HB];
 #pragma unroll
         for (int i = 0; i < S::HB * S::KX; ++i) w1[i] = W1F[64 * i + lane];
 #pragma unroll
-        for (int c = 0; c < S::KX; ++c) {
+        for (int c = 0; c < S::KX; ++c)
           xin[c] = *reinterpret_cast<const Fr*>(X + nrow * CL::XS + 16 * c + 4 * lg);
-          unsigned e[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) e[r] = X[(16 * jg + 4 * lg + r) * CL::XS + 16 * c + li];
-          x0T[c] = Fr{e[0] | (e[1] << 16), e[2] | (e[3] << 16)};
-        }
         f4 a1[S::HB];
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob)
@@ -917,9 +923,10 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
         }
         // every wavefront has finished reading the slots of the previous step
         __syncthreads();
+        // x0, dy and the activations are all in D layout (feature 4 lg + r,
+        // node li): each goes to the slot through the same transposing write
 #pragma unroll
-        for (int c = 0; c < S::KX; ++c)
-          *reinterpret_cast<Fr*>(slot + (CL::FX0 + c) * 512 + rdo) = x0T[c];
+        for (int c = 0; c < S::KX; ++c) put_t(CL::FX0 + c, xin[c]);
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob) {
           put_t(CL::FH1 + ob, h1[ob]);
@@ -934,10 +941,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll
         for (int qc = 0; qc < S::QB; ++qc) {
           dyf[qc] = to_frag<P>(*reinterpret_cast<const f4*>(D + nrow * CL::SD + 16 * qc + 4 * lg));
-          f4 v;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) v[r] = D[(16 * jg + 4 * lg + r) * CL::SD + 16 * qc + li];
-          *reinterpret_cast<Fr*>(slot + (CL::FDY + qc) * 512 + rdo) = to_frag<P>(v);
+          put_t(CL::FDY + qc, dyf[qc]);
         }
         // d2 = (W3^T dy) (1 - t2^2),  d1 = (W2^T d2) (1 - t1^2)
         f4 a2[S::HB];
