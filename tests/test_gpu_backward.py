@@ -101,34 +101,37 @@ def test_nlbm_adjoint_reduced_precision(lbm, prec):
     assert e_th < (2e-2 if prec == "bf16" else 3e-3)
 
 
-@pytest.mark.parametrize("prec,H,shape,batch,force", [
-    ("bf16", 64, (1, 256, 8), 8, 0),    # 2048 one-row items, 8 active lanes each
-    ("bf16", 64, (1, 200, 16), 12, 1),  # 2400 items, Kolmogorov force, ragged last step
-    ("fp16", 64, (1, 40, 300), 3, 1),   # 600 items of up to 64 nodes
-    ("bf16", 32, (1, 64, 200), 2, 0),
-    ("fp16", 32, (1, 33, 70), 2, 1),    # fewer items than workgroups
+@pytest.mark.parametrize("lat,prec,H,shape,batch,force", [
+    ("D2Q9", "bf16", 64, (1, 256, 8), 8, 0),    # 2048 one-row items, 8 active lanes each
+    ("D2Q9", "bf16", 64, (1, 200, 16), 12, 1),  # 2400 items, Kolmogorov force, ragged last step
+    ("D2Q9", "fp16", 64, (1, 40, 300), 3, 1),   # 600 items of up to 64 nodes
+    ("D2Q9", "bf16", 32, (1, 64, 200), 2, 0),
+    ("D2Q9", "fp16", 32, (1, 33, 70), 2, 1),    # fewer items than workgroups
+    ("D3Q19", "bf16", 32, (9, 10, 70), 2, 2),   # 360 items, three-component force, per-wave kernel
+    ("D3Q19", "fp16", 64, (6, 7, 20), 1, 0),    # the per-wave kernel at 16 bits
 ])
-def test_nlbm_adjoint_16bit_per_block(lbm, prec, H, shape, batch, force):
+def test_nlbm_adjoint_16bit_per_block(lbm, lat, prec, H, shape, batch, force):
     """16-bit adjoint on grids large enough that every workgroup runs several
     steps with all its wavefronts: each parameter block against the oracle's
     emulated-rounding adjoint, and additivity over nodes (the gradient with
     lam^{n+1} split between two disjoint node sets sums to the whole, since
     each node's contribution is formed the same way in both runs)."""
     nz, ny, nx = shape
-    kw = dict(force_kind=1, force_amp=1e-3, force_k=1) if force else {}
-    ocfg = oracle.Config(nx=nx, ny=ny, batch=batch, tau=0.51, hidden=H, out_scale=0.25,
-                         quant=prec, **kw)
-    theta = params(9, H, seed=31)
+    kw = {1: dict(force_kind=1, force_amp=1e-3, force_k=1),
+          2: dict(force_kind=2, force_amp=1e-3, force_k=1)}.get(force, {})
+    ocfg = oracle.Config(lattice=lat, nx=nx, ny=ny, nz=nz, batch=batch, tau=0.51, hidden=H,
+                         out_scale=0.25, quant=prec, **kw)
+    Q = ocfg.Q
+    theta = params(Q, H, seed=31)
     g = random_state(ocfg, 32, scale=0.03)
     lam1 = random_state(ocfg, 33, scale=1.0)
     want, wdth = oracle.step_adjoint(ocfg, g, lam1, theta.astype(np.float64))
     got, gdth = gpu_adjoint(lbm, ocfg, g, lam1, theta, prec=prec)
     e_lam = rel_l2(got, want)
-    Q = 9
     offs = [0, H * Q, H * Q + H, H * Q + H + H * H, H * Q + 2 * H + H * H,
             H * Q + 2 * H + H * H + Q * H, gdth.size]
     errs = [rel_l2(gdth[a:b], wdth[a:b]) for a, b in zip(offs[:-1], offs[1:])]
-    print(f"{prec} H={H} {shape} x{batch}: lam {e_lam:.2e}, blocks " +
+    print(f"{lat} {prec} H={H} {shape} x{batch}: lam {e_lam:.2e}, blocks " +
           " ".join(f"{e:.1e}" for e in errs))
     assert e_lam < (2e-3 if prec == "bf16" else 3e-4)
     for e in errs:
@@ -138,7 +141,7 @@ def test_nlbm_adjoint_16bit_per_block(lbm, prec, H, shape, batch, force):
     # are drawn there and carried to the canonical layout the helper takes.
     mask = np.random.default_rng(34).random(lam1.shape[:1] + lam1.shape[2:]) < 0.5
     ms = np.broadcast_to(np.expand_dims(mask, 1), lam1.shape).astype(np.float64)
-    m = to_canonical(ms, "D2Q9") > 0.5
+    m = to_canonical(ms, lat) > 0.5
     l1, d1 = gpu_adjoint(lbm, ocfg, g, np.where(m, lam1, 0.0), theta, prec=prec)
     l2, d2 = gpu_adjoint(lbm, ocfg, g, np.where(m, 0.0, lam1), theta, prec=prec)
     e_add = rel_l2(d1 + d2, gdth)
