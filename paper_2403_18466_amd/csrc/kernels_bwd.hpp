@@ -559,12 +559,19 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
 //
 // Slot fragment layout: fragment f holds, for logical lane l = i + 16 g,
 // the four 16-bit values A[i][4 g + r] (feature i of the fragment's 16,
-// nodes 4 g + r of the group) at byte 512 f + 8 swz(l) + 2 r, with
+// nodes 4 g + r of the group) at byte 512 f + 8 slot_pos(swz(l)) + 2 r, with
 // swz(l) = l ^ ((l >> 4) & 3).  The transposing writes from the D layout
 // store two nodes per dword (neighbouring lanes exchange half of their
-// values first); the swizzle puts exactly two lanes of each such write on
-// every bank.
+// values first).  slot_pos permutes the 8-byte positions within each block
+// of 16 so that every such write puts one lane on each bank, both for 32
+// banks served 32 lanes at a time and for 64 banks served by the whole
+// wavefront; swz alone left two lanes of each 32-lane half on one bank.
+// The 64-bit reads stay conflict-free: each block of 16 positions is still
+// read by 16 consecutive lanes.
 // ---------------------------------------------------------------------------
+__device__ __host__ constexpr int slot_pos(int p) {
+  return p ^ (8 * ((p >> 4) & 1) + (((p >> 4) & 1) ^ ((p >> 5) & 1)));
+}
 template <class L, int H, int P>
 struct CoopLayout {
   using S = Shape<L::Q, H>;
@@ -802,7 +809,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 
   // contraction-layout addresses: this lane's read offset, and the write
   // offsets of its four D-layout values (feature 4 lg + r, node li)
-  const int rdo = 8 * (lane ^ ((lane >> 4) & 3));
+  const int rdo = 8 * slot_pos(lane ^ ((lane >> 4) & 3));
   // A transposed fragment is written two nodes per dword: lanes li and
   // li ^ 1 swap half of their four values, the even lane then holds
   // features 0 and 1 of both nodes, the odd lane features 2 and 3.
@@ -811,7 +818,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int r = 2 * (li & 1) + j;
-    wro[j] = 8 * (4 * lg + (r ^ (li >> 2)) + 16 * (li >> 2)) + 4 * ((li & 3) >> 1);
+    wro[j] = 8 * slot_pos(4 * lg + (r ^ (li >> 2)) + 16 * (li >> 2)) + 4 * ((li & 3) >> 1);
   }
 
   // workgroup range of items; wavefront w takes item k + w of each step
