@@ -42,16 +42,26 @@ def unrolled_loss_and_grad(L: "lbm.Lattice", A0, theta, u_target, nsteps: int, c
     dL/dA) when given (e.g. the population loss on a node subset).  Forward
     keeps the state at every multiple of `ckpt` (plus A0); the backward pass
     walks the segments in reverse, recomputes each segment's states from its
-    checkpoint, and applies lbm_step_backward step by step.  Memory:
+    checkpoint, and applies lbm_step_backward step by step.  The last
+    segment's states are kept as the forward pass makes them (its backward
+    pass comes next and would recompute the same values).  Memory:
     nsteps/ckpt checkpoints + ckpt segment states + 2 adjoint buffers.
     Returns (loss [1] float64 device tensor, dtheta, dA0 or None)."""
     assert nsteps >= 1 and ckpt >= 1
+    last = ((nsteps - 1) // ckpt) * ckpt  # first step of the last segment
     ckpts = {0: A0}
+    kept = {}  # states last + 1 .. nsteps - 1
     a = A0.detach().clone()
-    b = L.empty_state()
+    spare = L.empty_state()
     for n in range(nsteps):
-        res = lbm.lbm_step(L.ctx, L.cfg, a, b, theta, 1)
-        a, b = res, (a if res is b else b)
+        keep = last < n + 1 < nsteps
+        out = L.empty_state() if keep else spare
+        lbm.lbm_step(L.ctx, L.cfg, a, out, theta, 1)
+        if not any(a is t for t in kept.values()):
+            spare = a  # a ping-pong buffer, free again
+        a = out
+        if keep:
+            kept[n + 1] = out
         if (n + 1) % ckpt == 0 and n + 1 < nsteps:
             ckpts[n + 1] = a.clone()
     if loss_fn is None:
@@ -66,6 +76,9 @@ def unrolled_loss_and_grad(L: "lbm.Lattice", A0, theta, u_target, nsteps: int, c
         start = ((n - 1) // ckpt) * ckpt
         seg = [ckpts[start]]
         for m in range(start, n - 1):
+            if m + 1 in kept:
+                seg.append(kept.pop(m + 1))
+                continue
             out = L.empty_state()
             lbm.lbm_step(L.ctx, L.cfg, seg[-1], out, theta, 1)
             seg.append(out)
