@@ -535,6 +535,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   const int per = (nitems + nw - 1) / nw;
   const int it0 = wv * per, it1 = min(it0 + per, nitems);
 
+  const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * Q) * 4u;
+  const rsrc_t src = make_rsrc(Ain, bytes), dst = make_rsrc(Aout, bytes);
+  // the first item's populations are loaded while the weights are staged
+  ItemWalk cur, nxt;
+  float gn[Q];
+  if (it0 < it1) {
+    cur.start(it0, nxc, G);
+    gather_item<L>(src, G, cur.item(G, lane), gn);
+  }
+
   // The weight fragments reach the registers through the (still unused)
   // tile memory: the workgroup stages them from coalesced reads of theta,
   // then every wave loads its copy with lane-contiguous reads.
@@ -550,9 +560,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   }
   if (it0 >= it1) return;
 
-  const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * Q) * 4u;
-  const rsrc_t src = make_rsrc(Ain, bytes), dst = make_rsrc(Aout, bytes);
-
   // the input columns past the populations never change: a constant 1 for
   // the bias of layer 1, then zeros
 #pragma unroll
@@ -565,10 +572,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     }
   }
 
-  ItemWalk cur, nxt;
-  cur.start(it0, nxc, G);
-  float gn[Q];
-  gather_item<L>(src, G, cur.item(G, lane), gn);
   for (int it = it0; it < it1; ++it) {
     // this item's populations go to the LDS tile; the next item's loads are
     // issued before the network runs
