@@ -231,6 +231,26 @@ lbm_status lbm_step_backward(lbm_ctx* ctx, const float* A_n, const float* theta,
                              const float* lam_n1, float* lam_n, float* dtheta, void* ws,
                              size_t ws_bytes, hipStream_t stream);
 
+/* The adjoint of nsteps consecutive lbm_step calls, the backward pass over
+ * one checkpoint segment of the SI's unrolled training: for m = nsteps - 1
+ * down to 0, lbm_step_backward with A_n = A[m], giving
+ *   lam^m   = (dA^{m+1}/dA^m)^T lam^{m+1}
+ *   dtheta += sum over m of (dA^{m+1}/dtheta)^T lam^{m+1}.
+ * A: host array of nsteps device pointers, A[m] the state the m-th step read
+ * (a population array each).  lam_a holds lam^{nsteps} on entry; lam_a and
+ * lam_b then take the outputs in turn, so lam^0 ends in lam_b for odd
+ * nsteps and in lam_a for even (lam_a is overwritten when nsteps >= 2).
+ * lam_a and lam_b must differ and alias no state.  For the tanh networks
+ * (hidden > 0, LBM_NET_TANH) the per-workgroup partial gradients of all the
+ * steps are summed in ws (in step order, so the result is bit-reproducible)
+ * and reduced into dtheta once; it equals the step-by-step sum up to float32
+ * rounding order.  Plain BGK and LBM_NET_LEAKY_300_300_100 run the steps
+ * through lbm_step_backward.  Errors as lbm_step_backward, plus
+ * LBM_ERR_INVALID for nsteps < 1 or a null entry of A. */
+lbm_status lbm_step_backward_seq(lbm_ctx* ctx, const float* const* A, int32_t nsteps,
+                                 const float* theta, float* lam_a, float* lam_b, float* dtheta,
+                                 void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Velocity mean-squared error of a pull-shifted state against a target
  * field (the training loss, a mean rather than the sum of eq. nn-loss, on
  * velocities rather than populations):

@@ -208,7 +208,7 @@ template <class L, int H, int P>
 __global__ __launch_bounds__(256) void nlbm_backward_kernel(
     const float* __restrict__ A, const float* __restrict__ theta, const float* __restrict__ lam1,
     float* __restrict__ lam0, float* __restrict__ part, Grid G, Force Fc, float rho0,
-    float omega, float knn, int nitems, int nxc) {
+    float omega, float knn, int nitems, int nxc, int accum) {
   using S = Shape<L::Q, H>;
   using BL = BwdLayout<L, H, P>;
   using Fr = typename Frag<P>::T;
@@ -538,8 +538,10 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
   }
   __syncthreads();
   float* pb = part + (size_t)blockIdx.x * S::n;
-  for (int i = threadIdx.x; i < S::n; i += 256)
-    pb[i] = ((lds[i] + lds[S::n + i]) + lds[2 * S::n + i]) + lds[3 * S::n + i];
+  for (int i = threadIdx.x; i < S::n; i += 256) {
+    const float v = ((lds[i] + lds[S::n + i]) + lds[2 * S::n + i]) + lds[3 * S::n + i];
+    pb[i] = accum ? pb[i] + v : v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -780,7 +782,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void
 nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__ theta,
                           const float* __restrict__ lam1, float* __restrict__ lam0,
                           float* __restrict__ part, Grid G, Force Fc, float rho0, float omega,
-                          float knn, int nitems, int nxc) {
+                          float knn, int nitems, int nxc, int accum) {
   using S = Shape<L::Q, H>;
   using CL = CoopLayout<L, H, P>;
   using Fr = typename Frag<P>::T;
@@ -1005,7 +1007,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   coop_put_of<CL>(wave, acc, red, lg, li);
   __syncthreads();
   float* pb = part + (size_t)blockIdx.x * S::n;
-  for (int i = threadIdx.x; i < S::n; i += blockDim.x) pb[i] = red[i];
+  for (int i = threadIdx.x; i < S::n; i += blockDim.x) pb[i] = accum ? pb[i] + red[i] : red[i];
 }
 
 // dtheta[p] += sum over the nb block partials part[b][p], in float64.
@@ -1036,10 +1038,13 @@ static __global__ __launch_bounds__(1024) void grad_reduce_kernel(const float* _
   }
 }
 
-// Launch of nlbm_backward_kernel<L, H, P>, defined in nlbm_bwd.hip.
+// Launch of the adjoint kernel for (lattice, H, precision), defined in
+// nlbm_bwd.hip.  Each workgroup writes its partial gradient to its row of
+// part (accum = 0) or adds it to what the row holds (accum = 1, for the
+// steps of a sequence that share one reduction).
 hipError_t nlbm_bwd_launch(bool d3q19, int hidden, int prec, unsigned blocks, hipStream_t s,
                            const float* A, const float* theta, const float* lam1, float* lam0,
                            float* part, Grid G, Force Fc, float rho0, float omega, float knn,
-                           int nitems, int nxc);
+                           int nitems, int nxc, int accum);
 
 }  // namespace lbm

@@ -407,9 +407,12 @@ lbm_status one_step(lbm_ctx* ctx, const float* Ain, float* Aout, const float* th
 }
 
 // ----------------------------------------------------------------- backward
+// accum: add this step's per-workgroup partials to those in ws instead of
+// overwriting them; reduce: sum the partials into dtheta after the step.
 template <class L, int H, int P>
 lbm_status launch_bwd(lbm_ctx* ctx, const float* A, const float* theta, const float* lam1,
-                      float* lam0, float* dtheta, void* ws, hipStream_t s) {
+                      float* lam0, float* dtheta, void* ws, hipStream_t s, int accum,
+                      bool reduce) {
   Grid G = grid_of(ctx->cfg);
   int nxc = (G.nx + 63) / 64;
   long long nitems = (long long)nxc * G.ny * G.nz * G.batch;
@@ -420,9 +423,10 @@ lbm_status launch_bwd(lbm_ctx* ctx, const float* A, const float* theta, const fl
   const unsigned blocks = bwd_blocks(ctx->ncu);
   hipError_t e = nlbm_bwd_launch(L::Q == 19, H, P, blocks, s, A, theta, lam1, lam0, part, G,
                                  force_of(c), (float)c.rho0, (float)(1.0 / c.tau),
-                                 (float)(c.out_scale / c.tau), (int)nitems, nxc);
+                                 (float)(c.out_scale / c.tau), (int)nitems, nxc, accum);
   if (e != hipSuccess)
     return fail(LBM_ERR_HIP, std::string("launch of nlbm_backward_kernel: ") + hipGetErrorString(e));
+  if (!reduce) return LBM_OK;
   hipLaunchKernelGGL(grad_reduce_kernel, dim3(blocks_for(nparam, 64)), dim3(1024), 0, s, part,
                      (int)blocks, nparam, dtheta);
   LBM_LAUNCHED("grad_reduce_kernel");
@@ -431,17 +435,22 @@ lbm_status launch_bwd(lbm_ctx* ctx, const float* A, const float* theta, const fl
 
 template <class L, int H>
 lbm_status launch_bwd_p(lbm_ctx* ctx, const float* A, const float* theta, const float* lam1,
-                        float* lam0, float* dtheta, void* ws, hipStream_t s) {
+                        float* lam0, float* dtheta, void* ws, hipStream_t s, int accum,
+                        bool reduce) {
   switch (ctx->cfg.mlp_prec) {
-    case LBM_MLP_FP32: return launch_bwd<L, H, P_F32>(ctx, A, theta, lam1, lam0, dtheta, ws, s);
-    case LBM_MLP_BF16: return launch_bwd<L, H, P_BF16>(ctx, A, theta, lam1, lam0, dtheta, ws, s);
-    default: return launch_bwd<L, H, P_F16>(ctx, A, theta, lam1, lam0, dtheta, ws, s);
+    case LBM_MLP_FP32:
+      return launch_bwd<L, H, P_F32>(ctx, A, theta, lam1, lam0, dtheta, ws, s, accum, reduce);
+    case LBM_MLP_BF16:
+      return launch_bwd<L, H, P_BF16>(ctx, A, theta, lam1, lam0, dtheta, ws, s, accum, reduce);
+    default:
+      return launch_bwd<L, H, P_F16>(ctx, A, theta, lam1, lam0, dtheta, ws, s, accum, reduce);
   }
 }
 
 template <class L>
 lbm_status run_backward(lbm_ctx* ctx, const float* A, const float* theta, const float* lam1,
-                        float* lam0, float* dtheta, void* ws, hipStream_t s) {
+                        float* lam0, float* dtheta, void* ws, hipStream_t s, int accum = 0,
+                        bool reduce = true) {
   const lbm_config& c = ctx->cfg;
   if (c.hidden == 0) {
     Grid G = grid_of(c);
@@ -452,8 +461,9 @@ lbm_status run_backward(lbm_ctx* ctx, const float* A, const float* theta, const 
     LBM_LAUNCHED("bgk_backward_kernel");
     return LBM_OK;
   }
-  if (c.hidden == 32) return launch_bwd_p<L, 32>(ctx, A, theta, lam1, lam0, dtheta, ws, s);
-  return launch_bwd_p<L, 64>(ctx, A, theta, lam1, lam0, dtheta, ws, s);
+  if (c.hidden == 32)
+    return launch_bwd_p<L, 32>(ctx, A, theta, lam1, lam0, dtheta, ws, s, accum, reduce);
+  return launch_bwd_p<L, 64>(ctx, A, theta, lam1, lam0, dtheta, ws, s, accum, reduce);
 }
 
 template <class L>
@@ -704,6 +714,53 @@ lbm_status lbm_step_backward(lbm_ctx* ctx, const float* A_n, const float* theta,
   if (ctx->cfg.lattice == LBM_D2Q9)
     return run_backward<D2Q9>(ctx, A_n, theta, lam_n1, lam_n, dtheta, ws, stream);
   return run_backward<D3Q19>(ctx, A_n, theta, lam_n1, lam_n, dtheta, ws, stream);
+  LBM_GUARD_END
+}
+
+lbm_status lbm_step_backward_seq(lbm_ctx* ctx, const float* const* A, int32_t nsteps,
+                                 const float* theta, float* lam_a, float* lam_b, float* dtheta,
+                                 void* ws, size_t ws_bytes, hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  lbm_status st = check_ctx(ctx);
+  if (st != LBM_OK) return st;
+  if (nsteps < 1) return fail(LBM_ERR_INVALID, "nsteps must be >= 1");
+  if (!A || !lam_a || !lam_b) return fail(LBM_ERR_INVALID, "null array");
+  if (lam_a == lam_b) return fail(LBM_ERR_INVALID, "lam_a and lam_b must differ");
+  for (int m = 0; m < nsteps; ++m) {
+    if (!A[m]) return fail(LBM_ERR_INVALID, "null state in A");
+    if (A[m] == lam_a || A[m] == lam_b)
+      return fail(LBM_ERR_INVALID, "lam_a and lam_b must not alias a state");
+  }
+  const lbm_config& c = ctx->cfg;
+  // the kernels that leave one partial gradient per workgroup sum the
+  // partials of all steps in ws and reduce them once; the others (plain
+  // BGK, the SI's network) run lbm_step_backward step by step
+  const bool shared = c.hidden != 0 && c.net != LBM_NET_LEAKY_300_300_100 &&
+                      c.collision == LBM_COLLISION_BGK;
+  if (shared) {
+    if (!theta || !dtheta) return fail(LBM_ERR_INVALID, "theta and dtheta must be given");
+    if (!ws) return fail(LBM_ERR_INVALID, "workspace is null");
+    if (ws_bytes < lbm_workspace_bytes(ctx))
+      return fail(LBM_ERR_WORKSPACE, "workspace smaller than lbm_workspace_bytes()");
+  }
+  float* in = lam_a;
+  float* out = lam_b;
+  for (int m = nsteps - 1; m >= 0; --m) {
+    if (shared) {
+      const int accum = m != nsteps - 1;
+      const bool reduce = m == 0;
+      st = c.lattice == LBM_D2Q9
+               ? run_backward<D2Q9>(ctx, A[m], theta, in, out, dtheta, ws, stream, accum, reduce)
+               : run_backward<D3Q19>(ctx, A[m], theta, in, out, dtheta, ws, stream, accum, reduce);
+    } else {
+      st = lbm_step_backward(ctx, A[m], theta, in, out, dtheta, ws, ws_bytes, stream);
+    }
+    if (st != LBM_OK) return st;
+    float* t = in;
+    in = out;
+    out = t;
+  }
+  return LBM_OK;
   LBM_GUARD_END
 }
 

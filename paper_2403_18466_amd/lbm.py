@@ -33,7 +33,7 @@ COLLISIONS = {"bgk": LBM_COLLISION_BGK, "smagorinsky": LBM_COLLISION_SMAGORINSKY
 EXPORTS = (
     "lbm_create", "lbm_destroy", "lbm_state_elems", "lbm_param_elems", "lbm_workspace_bytes",
     "lbm_lattice_tables", "lbm_init", "lbm_step", "lbm_moments", "lbm_shift",
-    "lbm_step_backward", "lbm_loss_velocity_mse", "lbm_adam", "lbm_box_filter",
+    "lbm_step_backward", "lbm_step_backward_seq", "lbm_loss_velocity_mse", "lbm_adam", "lbm_box_filter",
     "lbm_subsample", "lbm_loss_population_sse", "lbm_structure_functions",
     "lbm_mrt_moment_sums", "lbm_status_str", "lbm_last_error",
 )
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_moments": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "lbm_shift": ([vp, vp, vp, i32, vp], ctypes.c_int),
         "lbm_step_backward": ([vp, vp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "lbm_step_backward_seq": ([vp, vp, i32, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
         "lbm_loss_velocity_mse": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "lbm_adam": ([vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, dbl, i32, vp], ctypes.c_int),
         "lbm_box_filter": ([vp, vp, i32, i32, i32, i32, i32, i32, vp], ctypes.c_int),
@@ -261,6 +262,32 @@ def lbm_step_backward(ctx, cfg: Config, A_n, theta, lam_n1, lam_n, dtheta, ws, s
         _ptr(dtheta, torch.float32, npar, "dtheta", allow_none=cfg.hidden == 0),
         None if ws is None else ctypes.c_void_p(ws.data_ptr()), ws_bytes,
         _stream(stream)), "lbm_step_backward")
+
+
+def lbm_step_backward_seq(ctx, cfg: Config, states, theta, lam_a, lam_b, dtheta, ws, stream=None):
+    """Adjoint of len(states) consecutive steps, states[m] the state step m
+    read; lam_a holds dL/dA after the last step.  Returns the buffer that holds
+    dL/dA of states[0] (lam_b for an odd count, lam_a for even)."""
+    n = lbm_state_elems(ctx)
+    npar = lbm_param_elems(ctx)
+    nws = lbm_workspace_bytes(ctx)
+    if len(states) < 1:
+        raise ValueError("states must hold at least one state")
+    if ws is not None and (ws.device.type != "cuda" or not ws.is_contiguous()):
+        raise ValueError("ws must be a contiguous device tensor")
+    ws_bytes = 0 if ws is None else ws.numel() * ws.element_size()
+    if cfg.hidden and ws_bytes < nws:
+        raise ValueError(f"workspace of {ws_bytes} bytes, {nws} needed")
+    arr = (ctypes.c_void_p * len(states))(
+        *[_ptr(a, torch.float32, n, f"states[{m}]") for m, a in enumerate(states)])
+    _check(load_library().lbm_step_backward_seq(
+        ctx, arr, len(states),
+        _ptr(theta, torch.float32, npar, "theta", allow_none=cfg.hidden == 0),
+        _ptr(lam_a, torch.float32, n, "lam_a"), _ptr(lam_b, torch.float32, n, "lam_b"),
+        _ptr(dtheta, torch.float32, npar, "dtheta", allow_none=cfg.hidden == 0),
+        None if ws is None else ctypes.c_void_p(ws.data_ptr()), ws_bytes,
+        _stream(stream)), "lbm_step_backward_seq")
+    return lam_b if len(states) % 2 == 1 else lam_a
 
 
 def lbm_loss_velocity_mse(ctx, cfg: Config, A, u_target, loss, dLdA=None, stream=None):

@@ -42,7 +42,8 @@ def unrolled_loss_and_grad(L: "lbm.Lattice", A0, theta, u_target, nsteps: int, c
     dL/dA) when given (e.g. the population loss on a node subset).  Forward
     keeps the state at every multiple of `ckpt` (plus A0); the backward pass
     walks the segments in reverse, recomputes each segment's states from its
-    checkpoint, and applies lbm_step_backward step by step.  The last
+    checkpoint, and runs the segment's adjoint steps (lbm_step_backward_seq:
+    the per-workgroup gradient partials of a segment are reduced once).  The last
     segment's states are kept as the forward pass makes them (its backward
     pass comes next and would recompute the same values).  Memory:
     nsteps/ckpt checkpoints + ckpt segment states + 2 adjoint buffers.
@@ -82,8 +83,9 @@ def unrolled_loss_and_grad(L: "lbm.Lattice", A0, theta, u_target, nsteps: int, c
             out = L.empty_state()
             lbm.lbm_step(L.ctx, L.cfg, seg[-1], out, theta, 1)
             seg.append(out)
-        for m in range(n - 1, start - 1, -1):
-            lbm.lbm_step_backward(L.ctx, L.cfg, seg[m - start], theta, lam, lam_next, dtheta, ws)
+        # the segment's adjoint steps, with one reduction of the gradient
+        res = lbm.lbm_step_backward_seq(L.ctx, L.cfg, seg, theta, lam, lam_next, dtheta, ws)
+        if res is lam_next:
             lam, lam_next = lam_next, lam
         n = start
     return loss, dtheta, (lam if want_dA0 else None)

@@ -255,3 +255,47 @@ def test_unrolled_gradient_d3q19(lbm, prec):
     print(f"D3Q19 {prec} unrolled gradient rel L2 {e:.2e}")
     assert abs(host(loss)[0] - wl) < (1e-5 if prec == "fp32" else 1e-3) * wl
     assert e < (1e-4 if prec == "fp32" else 3e-2)
+
+
+@pytest.mark.parametrize("lat,prec,H,shape,nsteps", [
+    ("D2Q9", "bf16", 64, (1, 48, 70), 3),   # cooperative kernel, odd count
+    ("D2Q9", "fp16", 32, (1, 33, 64), 4),   # cooperative kernel, even count
+    ("D2Q9", "fp32", 64, (1, 20, 40), 2),   # per-wave kernel
+    ("D3Q19", "bf16", 64, (6, 7, 20), 3),   # per-wave kernel, 16-bit
+    ("D2Q9", "bgk", 0, (1, 16, 16), 3),     # no parameters: steps one by one
+])
+def test_backward_seq_matches_steps(lbm, lat, prec, H, shape, nsteps):
+    """lbm_step_backward_seq over a segment against lbm_step_backward step by
+    step: lam^0 bit-identical (the data path is the same kernel), and dtheta
+    equal up to the float32 order of summing the steps (partials summed
+    across steps in the workspace, then over workgroups)."""
+    nz, ny, nx = shape
+    ocfg = oracle.Config(lattice=lat, nx=nx, ny=ny, nz=nz, batch=2, tau=0.51,
+                         hidden=H, out_scale=0.25)
+    L = lbm.Lattice(lib_config(ocfg, "fp32" if prec == "bgk" else prec))
+    th = dev(params(ocfg.Q, H, seed=41)) if H else None
+    states = [dev(to_shifted(random_state(ocfg, 50 + m, scale=0.03), lat)) for m in range(nsteps)]
+    lam_in = dev(to_shifted(random_state(ocfg, 60, scale=1.0), lat))
+    # step by step
+    dth1 = torch.zeros(L.n_param, dtype=torch.float32, device="cuda") if H else None
+    lam = lam_in.clone()
+    for m in range(nsteps - 1, -1, -1):
+        lam, _ = L.step_backward(states[m], th, lam, dth1)
+    # one sequence call; dtheta accumulates onto what it holds
+    dth2 = torch.full((L.n_param,), 0.5, dtype=torch.float32, device="cuda") if H else None
+    a, b = lam_in.clone(), torch.empty_like(lam_in)
+    ws = L.workspace() if H else None
+    res = lbm.lbm_step_backward_seq(L.ctx, L.cfg, states, th, a, b, dth2, ws)
+    assert res is (b if nsteps % 2 else a)
+    assert torch.equal(res, lam)
+    if H:
+        d1, d2 = host(dth1), host(dth2) - 0.5
+        err = np.abs(d2 - d1).max() / np.abs(d1).max()
+        print(f"{lat} {prec} H={H} x{nsteps}: dtheta max rel diff {err:.1e}")
+        assert err < 2e-6
+    # argument errors come back as status codes, before any launch
+    with pytest.raises(RuntimeError):
+        lbm.lbm_step_backward_seq(L.ctx, L.cfg, states, th, a, a, dth2, ws)
+    with pytest.raises(RuntimeError):
+        lbm.lbm_step_backward_seq(L.ctx, L.cfg, [a] + states[1:], th, a, b, dth2, ws)
+    L.close()
