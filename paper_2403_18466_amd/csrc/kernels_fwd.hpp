@@ -506,6 +506,13 @@ struct StepLds {
   static constexpr int min_waves(int prec, bool forced) {
     return (L::Q == 19 && prec != P_F32 && !forced) ? 3 : 1;
   }
+  // wavefronts per workgroup: the unforced 16-bit instances run one
+  // workgroup per compute unit (four wavefronts per SIMD for D2Q9, three for
+  // D3Q19), so that the weights are staged once per compute unit and each
+  // thread stages a quarter as many of them; the others run workgroups of 4
+  static constexpr int waves_per_block(int prec, bool forced) {
+    return (prec == P_F32 || forced) ? 4 : (L::Q == 19 ? 12 : 16);
+  }
 };
 
 // FORCED: the body force of eq. fext is applied (Force::kind != 0).  The
@@ -513,8 +520,9 @@ struct StepLds {
 // 64-bit argument reduction): 108 instead of 149 registers per lane for the
 // 16-bit D2Q9 instance, 158 instead of 216 for D3Q19.
 template <class L, int H, int P, bool FORCED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    StepLds<L, H>::min_waves(P, FORCED)))) void nlbm_step_kernel(const float* __restrict__ Ain,
+__global__ __launch_bounds__((64 * StepLds<L, H>::waves_per_block(P, FORCED)))
+__attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void nlbm_step_kernel(
+                                                        const float* __restrict__ Ain,
                                                         float* __restrict__ Aout,
                                                         const float* __restrict__ theta, Grid G,
                                                         Force Fc, float rho0, float omega,
@@ -522,8 +530,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   using S = Shape<L::Q, H>;
   using LD = StepLds<L, H>;
   using F = typename Frag<P>::T;
-  constexpr int Q = L::Q;
-  __shared__ __attribute__((aligned(16))) float lds[4 * LD::per_wave];
+  constexpr int Q = L::Q, WB = LD::waves_per_block(P, FORCED);
+  __shared__ __attribute__((aligned(16))) float lds[WB * LD::per_wave];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, lg = lane >> 4, li = lane & 15;
   float* X = lds + wave * LD::per_wave;
@@ -531,7 +539,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
 
   const int nb = gridDim.x, bid = blockIdx.x;
   const int lb = (nb % 8 == 0) ? (bid % 8) * (nb / 8) + bid / 8 : bid;
-  const int nw = nb * 4, wv = lb * 4 + wave;
+  const int nw = nb * WB, wv = lb * WB + wave;
   const int per = (nitems + nw - 1) / nw;
   const int it0 = wv * per, it1 = min(it0 + per, nitems);
 
@@ -552,9 +560,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
   {
     using F = typename Frag<P>::T;
     constexpr int NF = S::HB * S::KX + S::HB * S::HB + S::QB * S::HB;
-    static_assert(NF * 64 * (int)sizeof(F) <= 4 * LD::per_wave * 4, "fragment staging");
+    static_assert(NF * 64 * (int)sizeof(F) <= WB * LD::per_wave * 4, "fragment staging");
     F* fr = reinterpret_cast<F*>(lds);
-    stage_weight_fragments<P, S, 256>(fr, theta);
+    stage_weight_fragments<P, S, 64 * WB>(fr, theta);
     W.load_staged(fr, theta);
     __syncthreads();
   }

@@ -308,10 +308,10 @@ lbm_status launch_bgk(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t s
 // Workgroups for a persistent kernel: as many as fit on the chip at once,
 // no more than there are work units, a multiple of the 8 XCDs when large.
 template <class K>
-lbm_status persistent_blocks(lbm_ctx* ctx, K kernel, long long units_per_block_min,
+lbm_status persistent_blocks(lbm_ctx* ctx, K kernel, int threads, long long units_per_block_min,
                              long long units, unsigned& blocks) {
   int occ = 0;
-  LBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 256, 0));
+  LBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0));
   if (occ < 1) occ = 1;
   long long want = (long long)ctx->ncu * occ;
   long long cap = (units + units_per_block_min - 1) / units_per_block_min;
@@ -333,10 +333,11 @@ lbm_status launch_nlbm(lbm_ctx* ctx, const float* Ain, float* Aout, const float*
   // forced and unforced instances: the unforced one needs fewer registers
   const bool forced = c.force_kind != LBM_FORCE_NONE;
   const auto kernel = forced ? nlbm_step_kernel<L, H, P, true> : nlbm_step_kernel<L, H, P, false>;
+  const int wb = StepLds<L, H>::waves_per_block(P, forced);
   unsigned blocks = 0;
-  lbm_status st = persistent_blocks(ctx, kernel, 4, nitems, blocks);
+  lbm_status st = persistent_blocks(ctx, kernel, 64 * wb, wb, nitems, blocks);
   if (st != LBM_OK) return st;
-  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(256), 0, s, Ain, Aout, theta, G, force_of(c),
+  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(64 * wb), 0, s, Ain, Aout, theta, G, force_of(c),
                      (float)c.rho0, (float)(1.0 / c.tau), (float)(c.out_scale / c.tau),
                      (int)nitems, nxc);
   LBM_LAUNCHED("nlbm_step_kernel");
