@@ -557,13 +557,14 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
   // tile memory: the workgroup stages them from coalesced reads of theta,
   // then every wave loads its copy with lane-contiguous reads.
   Weights<P, S> W;
+  W.load_biases(theta);
   {
     using F = typename Frag<P>::T;
     constexpr int NF = S::HB * S::KX + S::HB * S::HB + S::QB * S::HB;
     static_assert(NF * 64 * (int)sizeof(F) <= WB * LD::per_wave * 4, "fragment staging");
     F* fr = reinterpret_cast<F*>(lds);
     stage_weight_fragments<P, S, 64 * WB>(fr, theta);
-    W.load_staged(fr, theta);
+    W.load_staged(fr);
     __syncthreads();
   }
   if (it0 >= it1) return;

@@ -215,11 +215,27 @@ struct Weights {
   f4 b2[S::HB];
   f4 b3[S::QB];
 
-  // from the fragments staged in LDS (stage_weight_fragments), with b2 and
-  // b3 read from theta
-  __device__ inline void load_staged(const F* fr, const float* __restrict__ th) {
-    const int l = threadIdx.x & 63, g = l >> 4;
+  // b2 and b3 from theta (independent of the staging, so their reads can
+  // be in flight while it runs)
+  __device__ inline void load_biases(const float* __restrict__ th) {
+    const int g = (threadIdx.x & 63) >> 4;
     constexpr float sc = tanh_weight_scale<P>();
+#pragma unroll
+    for (int ob = 0; ob < S::HB; ++ob)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) b2[ob][r] = sc * th[S::ob2 + 16 * ob + 4 * g + r];
+#pragma unroll
+    for (int ob = 0; ob < S::QB; ++ob)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int q = 16 * ob + 4 * g + r;
+        b3[ob][r] = q < S::Q ? th[S::ob3 + q] : 0.f;
+      }
+  }
+
+  // the weight fragments, from those staged in LDS (stage_weight_fragments)
+  __device__ inline void load_staged(const F* fr) {
+    const int l = threadIdx.x & 63;
     constexpr int N1 = S::HB * S::KX, N2 = S::HB * S::HB;
 #pragma unroll
     for (int ob = 0; ob < S::HB; ++ob) {
@@ -227,19 +243,11 @@ struct Weights {
       for (int c = 0; c < S::KX; ++c) w1[ob][c] = fr[64 * (ob * S::KX + c) + l];
 #pragma unroll
       for (int c = 0; c < S::HB; ++c) w2[ob][c] = fr[64 * (N1 + ob * S::HB + c) + l];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) b2[ob][r] = sc * th[S::ob2 + 16 * ob + 4 * g + r];
     }
 #pragma unroll
-    for (int ob = 0; ob < S::QB; ++ob) {
+    for (int ob = 0; ob < S::QB; ++ob)
 #pragma unroll
       for (int c = 0; c < S::HB; ++c) w3[ob][c] = fr[64 * (N1 + N2 + ob * S::HB + c) + l];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int q = 16 * ob + 4 * g + r;
-        b3[ob][r] = q < S::Q ? th[S::ob3 + q] : 0.f;
-      }
-    }
   }
 
   // lane-local A-operand entry: row o, k = 16 c + 4 g + r
