@@ -263,6 +263,7 @@ def test_unrolled_gradient_d3q19(lbm, prec):
     ("D2Q9", "fp32", 64, (1, 20, 40), 2),   # per-wave kernel
     ("D3Q19", "bf16", 64, (6, 7, 20), 3),   # per-wave kernel, 16-bit
     ("D2Q9", "bgk", 0, (1, 16, 16), 3),     # no parameters: steps one by one
+    ("D2Q9", "bf16", 64, (1, 16, 70), 1),   # a single step
 ])
 def test_backward_seq_matches_steps(lbm, lat, prec, H, shape, nsteps):
     """lbm_step_backward_seq over a segment against lbm_step_backward step by
@@ -298,4 +299,19 @@ def test_backward_seq_matches_steps(lbm, lat, prec, H, shape, nsteps):
         lbm.lbm_step_backward_seq(L.ctx, L.cfg, states, th, a, a, dth2, ws)
     with pytest.raises(RuntimeError):
         lbm.lbm_step_backward_seq(L.ctx, L.cfg, [a] + states[1:], th, a, b, dth2, ws)
+    L.close()
+
+
+def test_backward_seq_smagorinsky_unsupported(lbm):
+    """The Smagorinsky collision has no adjoint: the sequence call reports
+    LBM_ERR_UNSUPPORTED like the single step, and writes nothing."""
+    ocfg = oracle.Config(nx=16, ny=16, tau=0.505, collision="smagorinsky", smag_cs=0.17)
+    L = lbm.Lattice(lib_config(ocfg))
+    states = [dev(to_shifted(random_state(ocfg, 70 + m, scale=0.03), "D2Q9")) for m in range(2)]
+    a = dev(to_shifted(random_state(ocfg, 72, scale=1.0), "D2Q9"))
+    a0, b = a.clone(), torch.zeros_like(a)
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_step_backward_seq(L.ctx, L.cfg, states, None, a, b, None, None)
+    assert e.value.status == lbm.LBM_ERR_UNSUPPORTED
+    assert torch.equal(a, a0) and not torch.any(b)
     L.close()
