@@ -50,21 +50,25 @@ def unrolled_loss_and_grad(L: "lbm.Lattice", A0, theta, u_target, nsteps: int, c
     Returns (loss [1] float64 device tensor, dtheta, dA0 or None)."""
     assert nsteps >= 1 and ckpt >= 1
     last = ((nsteps - 1) // ckpt) * ckpt  # first step of the last segment
-    ckpts = {0: A0}
+    a = A0.detach()  # read only: A0 is a checkpoint, never a free buffer
+    ckpts = {0: a}
     kept = {}  # states last + 1 .. nsteps - 1
-    a = A0.detach().clone()
     spare = L.empty_state()
     for n in range(nsteps):
         keep = last < n + 1 < nsteps
-        out = L.empty_state() if keep else spare
+        is_ckpt = (n + 1) % ckpt == 0 and n + 1 < nsteps
+        # kept states and checkpoints are written to buffers of their own
+        out = L.empty_state() if keep or is_ckpt else spare
         lbm.lbm_step(L.ctx, L.cfg, a, out, theta, 1)
-        if not any(a is t for t in kept.values()):
+        if not any(a is t for t in list(kept.values()) + list(ckpts.values())):
             spare = a  # a ping-pong buffer, free again
+        elif out is spare:
+            spare = L.empty_state()  # the input is still needed
         a = out
         if keep:
             kept[n + 1] = out
-        if (n + 1) % ckpt == 0 and n + 1 < nsteps:
-            ckpts[n + 1] = a.clone()
+        if is_ckpt:
+            ckpts[n + 1] = out
     if loss_fn is None:
         loss, lam = L.loss_velocity_mse(a, u_target, want_grad=True)
     else:
