@@ -539,16 +539,32 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
 
   const int nb = gridDim.x, bid = blockIdx.x;
   const int lb = (nb % 8 == 0) ? (bid % 8) * (nb / 8) + bid / 8 : bid;
-  const int nw = nb * WB, wv = lb * WB + wave;
-  const int per = (nitems + nw - 1) / nw;
-  const int it0 = wv * per, it1 = min(it0 + per, nitems);
+  // Items of this wavefront: it0, it0 + ST, ... below ib1.  D2Q9: a
+  // contiguous range per wavefront.  D3Q19: the workgroup's range with its
+  // wavefronts interleaved (wavefront w takes items ib0 + w, ib0 + w + WB,
+  // ...), so that neighbouring items, which share the cache lines of the
+  // x-shifted loads, are in flight on one compute unit at the same time; the
+  // step then reads 1.01x its algorithmic bytes instead of 1.06x.  For D2Q9
+  // the interleaving read more (1.04x against 1.03x) and ran 1% slower.
+  constexpr int ST = L::Q == 19 ? WB : 1;
+  int it0, ib1;
+  if constexpr (ST > 1) {
+    const int per = (nitems + nb - 1) / nb;
+    const int ib0 = min(lb * per, nitems);
+    ib1 = min(ib0 + per, nitems);
+    it0 = ib0 + wave;
+  } else {
+    const int nw = nb * WB, per = (nitems + nw - 1) / nw;
+    it0 = (lb * WB + wave) * per;
+    ib1 = min(it0 + per, nitems);
+  }
 
   const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * Q) * 4u;
   const rsrc_t src = make_rsrc(Ain, bytes), dst = make_rsrc(Aout, bytes);
   // the first item's populations are loaded while the weights are staged
   ItemWalk cur, nxt;
   float gn[Q];
-  if (it0 < it1) {
+  if (it0 < ib1) {
     cur.start(it0, nxc, G);
     gather_item<L>(src, G, cur.item(G, lane), gn);
   }
@@ -567,7 +583,7 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
     W.load_staged(fr);
     __syncthreads();
   }
-  if (it0 >= it1) return;
+  if (it0 >= ib1) return;
 
   // the input columns past the populations never change: a constant 1 for
   // the bias of layer 1, then zeros
@@ -581,14 +597,20 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
     }
   }
 
-  for (int it = it0; it < it1; ++it) {
+  for (int it = it0; it < ib1; it += ST) {
     // this item's populations go to the LDS tile; the next item's loads are
     // issued before the network runs
 #pragma unroll
     for (int q = 0; q < Q; ++q) X[lane * LD::SX + q] = gn[q];
-    nxt = cur;
-    nxt.next(nxc, G);
-    if (it + 1 < it1) gather_item<L>(src, G, nxt.item(G, lane), gn);
+    if (it + ST < ib1) {
+      if constexpr (ST > 1) {
+        nxt.start(it + ST, nxc, G);
+      } else {
+        nxt = cur;
+        nxt.next(nxc, G);
+      }
+      gather_item<L>(src, G, nxt.item(G, lane), gn);
+    }
     wave_lds_sync();
 #pragma unroll
     for (int jg = 0; jg < 4; ++jg) {
