@@ -141,9 +141,10 @@ typedef struct {
 
 /* Validate `cfg` and create a context holding a copy of it, bound to the
  * current device.  The context allocates one small device buffer
- * (12 KiB per field) for the float64 partial sums of lbm_moments and
- * lbm_loss_velocity_mse; calls that use one context must therefore be
- * ordered (one stream, or synchronised streams).  With
+ * (96 KiB per field) for the float64 partial sums of lbm_moments and the
+ * losses, and for D3Q19 one of 48 KiB for lbm_mrt_moment_sums; calls that
+ * use one context must therefore be ordered (one stream, or synchronised
+ * streams).  With
  * LBM_NET_LEAKY_300_300_100 it also holds the weights in the kernel's
  * fragment order (about 0.3 MB in bf16/fp16, 0.6 MB in fp32, refreshed from
  * theta by every lbm_step call) and its index table (0.6 MB), plus the
@@ -314,12 +315,15 @@ lbm_status lbm_loss_population_sse(lbm_ctx* ctx, const float* A, const float* ta
  *   S_abs[p-1][l-1] = < |u_a(x + l e_a) - u_a(x)|^p >,
  * means over every node, field and axis a (the longitudinal increment,
  * periodic).  S, S_abs: device float64 [pmax][lmax].  pmax <= 8, lmax <=
- * the smallest grid size.  Increments and sums in float64, fixed order.  The
- * context keeps a partial-sum buffer of lmax * 64 * 2 pmax doubles; a call
- * that needs a larger one than before reallocates it (and waits for the
- * device). */
+ * the smallest grid size.  Increments and sums in float64, fixed order.
+ * ws: caller-owned device workspace of at least
+ * lbm_structure_functions_workspace_bytes(ctx, lmax, pmax) bytes for the
+ * per-block partial sums (LBM_ERR_WORKSPACE if smaller); the call neither
+ * allocates nor waits for the device. */
+size_t lbm_structure_functions_workspace_bytes(const lbm_ctx* ctx, int32_t lmax, int32_t pmax);
 lbm_status lbm_structure_functions(lbm_ctx* ctx, const float* u, int32_t lmax, int32_t pmax,
-                                   double* S, double* S_abs, hipStream_t stream);
+                                   double* S, double* S_abs, void* ws, size_t ws_bytes,
+                                   hipStream_t stream);
 
 /* Sums of the SI's moment-space analysis of a collision (D3Q19 only; the
  * SI gives M for D3Q19).  A_n and A_n1 are consecutive states of lbm_step

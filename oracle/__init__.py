@@ -38,7 +38,7 @@ def build(force: bool = False) -> str:
         tmp = _LIB + ".tmp"
         subprocess.check_call([
             "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-            "-fno-fast-math", _SRC, "-o", tmp, "-lm"])
+            "-fno-fast-math", "-fopenmp", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -52,6 +52,7 @@ class _Cfg(ctypes.Structure):
         ("force_k", ctypes.c_int32), ("hidden", ctypes.c_int32),
         ("quant", ctypes.c_int32), ("out_scale", ctypes.c_double),
         ("net", ctypes.c_int32), ("collision", ctypes.c_int32), ("smag_cs", ctypes.c_double),
+        ("quant_weights", ctypes.c_int32),
     ]
 
 
@@ -83,6 +84,10 @@ def _load():
             ("orc_mrt_matrix", [ctypes.POINTER(ctypes.c_int32)]),
             ("orc_loss_population_sse", [cp, dp, dp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int,
                                          dp, dp]),
+            ("orc_adam", [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                          ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int]),
+            ("orc_box_filter", [ctypes.c_int] * 6 + [dp, dp]),
+            ("orc_set_threads", [ctypes.c_int]),
         ]:
             f = getattr(_lib, name)
             f.argtypes = args
@@ -119,12 +124,16 @@ class Config:
     net: str = "tanh"      # "tanh": Q-H-H-Q tanh; "paper": Q-300-300-100-Q LeakyReLU
     collision: str = "bgk"  # "bgk" or "smagorinsky" (BGK at the local tau_eff)
     smag_cs: float = 0.0
+    # with quant != "none": round every weight to the format (True), or take
+    # the weights as given (False: the caller passes the operand weights in
+    # effect; only the input and the hidden activations are rounded)
+    quant_weights: bool = True
 
     def _c(self) -> _Cfg:
         return _Cfg(LATTICES[self.lattice], self.nx, self.ny, self.nz, self.batch,
                     self.tau, self.rho0, self.force_kind, self.force_amp, self.force_k,
                     self.hidden, QUANT[self.quant], self.out_scale, NETS[self.net],
-                    COLLISIONS[self.collision], self.smag_cs)
+                    COLLISIONS[self.collision], self.smag_cs, int(bool(self.quant_weights)))
 
     @property
     def Q(self) -> int:
@@ -300,6 +309,44 @@ def mrt_moment_sums(cfg: Config, g_n, g_n1):
     out = np.empty((19, 5))
     c = cfg._c()
     _check(_load().orc_mrt_moment_sums(ctypes.byref(c), _ptr(a), _ptr(b), _ptr(out)), "mrt_moment_sums")
+    return out
+
+
+def set_threads(n: int) -> int:
+    """Host threads of the oracle's node loops (1 = serial, the default).
+    Node results do not depend on it; the adjoint's parameter gradient is
+    summed per thread and then in thread order.  Returns the count in use."""
+    return int(_load().orc_set_threads(int(n)))
+
+
+def default_threads() -> int:
+    """A thread count for the tests' larger oracle runs: the CPUs this
+    process may use, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def adam(p, grad, m, v, lr, beta1, beta2, eps, weight_decay, t):
+    """One Adam step with L2 weight decay, in float64, in place on p, m, v."""
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(grad, dtype=np.float64)
+    assert p.shape == g.shape == m.shape == v.shape
+    _check(_load().orc_adam(p.size, _ptr(p), _ptr(g), _ptr(m), _ptr(v), lr, beta1, beta2, eps,
+                            weight_decay, int(t)), "adam")
+
+
+def box_filter(src, factor: int):
+    """Block mean of [batch][channels][nz][ny][nx] fields over factor^D fine
+    nodes (nz untouched when it is 1)."""
+    src = np.ascontiguousarray(src, dtype=np.float64)
+    b, c, nz, ny, nx = src.shape
+    fz = factor if nz > 1 else 1
+    out = np.empty((b, c, nz // fz, ny // factor, nx // factor))
+    _check(_load().orc_box_filter(b, c, nx, ny, nz, factor, _ptr(src), _ptr(out)), "box_filter")
     return out
 
 

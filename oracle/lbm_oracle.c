@@ -34,6 +34,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Lattices                                                                  */
@@ -85,6 +88,10 @@ typedef struct {
     int32_t collision;  /* 0: BGK at tau; 1: BGK at the Smagorinsky tau_eff (hidden
                            must be 0) */
     double smag_cs;     /* Smagorinsky constant C_s (filter width = 1 lattice unit) */
+    int32_t quant_weights; /* with quant != 0: 1 rounds every weight to the format
+                              (the rounding points of the reduced-precision network);
+                              0 takes the weights as given, for a caller that
+                              supplies the operand weights in effect itself */
 } orc_config;
 
 typedef struct {
@@ -189,18 +196,12 @@ static double quantise(int quant, double v) {
     return v;
 }
 
-/* The weight a reduced-precision network reads.  A tanh is evaluated as
- * 1 - 2 / (1 + 2^(c z)) with c = 2 log2(e); the tanh layers carry c (as a
- * float32) in their operands, so the operand is the float32 product c w
- * rounded to the format and the weight in effect is that divided by c.
- * Other layers round w itself. */
-static const float TANH_SCALE = 2.8853900817779268f;
-
-static double qweight(int quant, int scaled, double w) {
-    if (!quant) return w;
-    if (!scaled) return quantise(quant, w);
-    double c = (double)TANH_SCALE;
-    return quantise(quant, (double)(float)(c * w)) / c;
+/* The weight a reduced-precision network reads: the stored float32 weight
+ * rounded to the operand format.  Biases are not rounding points (they are
+ * added to the float32 sums). */
+static double qweight(const orc_config *cfg, double w) {
+    if (!cfg->quant || !cfg->quant_weights) return w;
+    return quantise(cfg->quant, w);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -290,10 +291,10 @@ static double activation_slope(int leaky, double a, double t) {
 }
 
 /* The MLP of the SI: linear layers with the hidden activation after every
- * layer but the last.  In the emulated reduced-precision mode the network
- * input, the weights, the layer-1 bias and every hidden activation are
- * rounded (the weights and layer-1 bias of tanh layers as in qweight); the
- * other biases and all sums stay exact. */
+ * layer but the last.  In the emulated reduced-precision mode the rounding
+ * points are the network input, every weight and every hidden activation
+ * (after the exact activation function); the biases and all sums stay
+ * exact. */
 static void mlp_forward(const orc_config *cfg, const net_shape *n, const double *theta,
                         node_fwd *s) {
     int qt = cfg->quant;
@@ -303,10 +304,9 @@ static void mlp_forward(const orc_config *cfg, const net_shape *n, const double 
     for (int l = 0; l < n->nl; ++l) {
         int nin = n->width[l], nout = n->width[l + 1];
         const double *b = W + (int64_t)nout * nin;
-        int scaled = !n->leaky && l + 1 < n->nl;
         for (int o = 0; o < nout; ++o) {
-            double a = l == 0 ? qweight(qt, scaled, b[o]) : b[o];
-            for (int i = 0; i < nin; ++i) a += qweight(qt, scaled, W[(int64_t)o * nin + i]) * in[i];
+            double a = b[o];
+            for (int i = 0; i < nin; ++i) a += qweight(cfg, W[(int64_t)o * nin + i]) * in[i];
             if (l + 1 < n->nl) {
                 s->pre[l][o] = a;
                 s->t[l][o] = activation(n->leaky, a);
@@ -398,37 +398,97 @@ static inline int64_t wrap(int64_t i, int64_t n) {
     return r < 0 ? r + n : r;
 }
 
-/* One full step (collide at every node, then periodic streaming), on
- * canonical pre-collision deviations.  g_out must not alias g_in. */
-int orc_step(const orc_config *cfg, const double *theta, const double *g_in, double *g_out) {
+/* The parameters the network computes with.  With quant and quant_weights
+ * set this is a copy of theta whose weights are rounded to the format (the
+ * biases as given), and *eff is cfg with quant_weights cleared: the rounding
+ * of each weight is done once per call instead of once per node.  Otherwise
+ * theta itself and *eff = *cfg.  *owned receives the copy to free (or NULL). */
+static const double *effective_theta(const orc_config *cfg, const double *theta,
+                                     orc_config *eff, double **owned) {
+    *eff = *cfg;
+    *owned = NULL;
+    if (!theta || cfg->hidden <= 0 || !cfg->quant || !cfg->quant_weights) return theta;
     lattice_t L;
-    if (check_cfg(cfg, &L)) return -1;
-    int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q;
-    int64_t N = nx * ny * nz;
-    node_fwd *s = (node_fwd *)malloc(sizeof(node_fwd));
-    if (!s) return -2;
-    for (int64_t b = 0; b < cfg->batch; ++b) {
-        const double *gi = g_in + b * Q * N;
-        double *go = g_out + b * Q * N;
-        for (int64_t z = 0; z < nz; ++z)
-            for (int64_t y = 0; y < ny; ++y)
-                for (int64_t x = 0; x < nx; ++x) {
-                    int64_t n = (z * ny + y) * nx + x;
-                    for (int q = 0; q < Q; ++q) s->g[q] = gi[q * N + n];
-                    body_force(cfg, (int)x, (int)y, (int)z, s->F);
-                    double post[QMAX];
-                    collide_node(cfg, &L, theta, s, post);
-                    /* stream: f_q(x + c_q, t + 1) = f_q^post(x, t) */
-                    for (int q = 0; q < Q; ++q) {
-                        int64_t xd = wrap(x + L.c[q][0], nx);
-                        int64_t yd = wrap(y + L.c[q][1], ny);
-                        int64_t zd = wrap(z + L.c[q][2], nz);
-                        go[q * N + (zd * ny + yd) * nx + xd] = post[q];
-                    }
-                }
+    net_shape n;
+    if (get_lattice(cfg->lattice, &L) || get_net(L.Q, cfg->hidden, cfg->net, &n)) return theta;
+    int64_t P = orc_param_elems(cfg->lattice, cfg->hidden, cfg->net);
+    double *t = (double *)malloc(sizeof(double) * (size_t)P);
+    if (!t) return NULL;
+    int64_t o = 0;
+    for (int l = 0; l < n.nl; ++l) {
+        int64_t nw = (int64_t)n.width[l + 1] * n.width[l];
+        for (int64_t i = 0; i < nw; ++i) t[o + i] = qweight(cfg, theta[o + i]);
+        for (int64_t i = 0; i < n.width[l + 1]; ++i) t[o + nw + i] = theta[o + nw + i];
+        o += nw + n.width[l + 1];
     }
-    free(s);
-    return 0;
+    eff->quant_weights = 0;
+    *owned = t;
+    return t;
+}
+
+/* Host threads of the node loops.  Every node is computed on its own, in
+ * the same order of operations whatever the thread count; only the
+ * parameter-gradient sum of the adjoint is split into per-thread partial
+ * sums (added in thread order).  1 (the default) runs everything serially. */
+static int g_threads = 1;
+
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    g_threads = n < 1 ? 1 : n;
+#else
+    (void)n;
+    g_threads = 1;
+#endif
+    return g_threads;
+}
+
+/* One full step (collide at every node, then periodic streaming), on
+ * canonical pre-collision deviations.  g_out must not alias g_in.  The rows
+ * (field, z, y) are independent: each node writes its own Q destinations
+ * (streaming is a permutation). */
+int orc_step(const orc_config *cfg_in, const double *theta_in, const double *g_in, double *g_out) {
+    lattice_t L;
+    if (check_cfg(cfg_in, &L)) return -1;
+    orc_config cfg_eff;
+    double *owned;
+    const double *theta = effective_theta(cfg_in, theta_in, &cfg_eff, &owned);
+    if (theta_in && !theta) return -2;
+    const orc_config *cfg = &cfg_eff;
+    const int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q;
+    const int64_t N = nx * ny * nz, rows = (int64_t)cfg->batch * nz * ny;
+    int err = 0;
+#pragma omp parallel num_threads(g_threads)
+    {
+        node_fwd *s = (node_fwd *)malloc(sizeof(node_fwd));
+        if (!s) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(static)
+        for (int64_t r = 0; r < rows; ++r) {
+            if (!s) continue;
+            const int64_t b = r / (nz * ny), z = (r / ny) % nz, y = r % ny;
+            const double *gi = g_in + b * Q * N;
+            double *go = g_out + b * Q * N;
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t n = (z * ny + y) * nx + x;
+                for (int q = 0; q < Q; ++q) s->g[q] = gi[q * N + n];
+                body_force(cfg, (int)x, (int)y, (int)z, s->F);
+                double post[QMAX];
+                collide_node(cfg, &L, theta, s, post);
+                /* stream: f_q(x + c_q, t + 1) = f_q^post(x, t) */
+                for (int q = 0; q < Q; ++q) {
+                    int64_t xd = wrap(x + L.c[q][0], nx);
+                    int64_t yd = wrap(y + L.c[q][1], ny);
+                    int64_t zd = wrap(z + L.c[q][2], nz);
+                    go[q * N + (zd * ny + yd) * nx + xd] = post[q];
+                }
+            }
+        }
+        free(s);
+    }
+    free(owned);
+    return err;
 }
 
 /* nsteps steps in place on g (uses one scratch copy). */
@@ -449,25 +509,42 @@ int orc_run(const orc_config *cfg, const double *theta, double *g, int nsteps) {
 
 /* Post-collision populations of every node, without streaming (used by the
  * tests to pin the collision alone). */
-int orc_collide(const orc_config *cfg, const double *theta, const double *g_in, double *post_out) {
+int orc_collide(const orc_config *cfg_in, const double *theta_in, const double *g_in,
+                double *post_out) {
     lattice_t L;
-    if (check_cfg(cfg, &L)) return -1;
-    int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q, N = nx * ny * nz;
-    node_fwd *s = (node_fwd *)malloc(sizeof(node_fwd));
-    if (!s) return -2;
-    for (int64_t b = 0; b < cfg->batch; ++b)
-        for (int64_t z = 0; z < nz; ++z)
-            for (int64_t y = 0; y < ny; ++y)
-                for (int64_t x = 0; x < nx; ++x) {
-                    int64_t n = (z * ny + y) * nx + x;
-                    for (int q = 0; q < Q; ++q) s->g[q] = g_in[(b * Q + q) * N + n];
-                    body_force(cfg, (int)x, (int)y, (int)z, s->F);
-                    double post[QMAX];
-                    collide_node(cfg, &L, theta, s, post);
-                    for (int q = 0; q < Q; ++q) post_out[(b * Q + q) * N + n] = post[q];
-                }
-    free(s);
-    return 0;
+    if (check_cfg(cfg_in, &L)) return -1;
+    orc_config cfg_eff;
+    double *owned;
+    const double *theta = effective_theta(cfg_in, theta_in, &cfg_eff, &owned);
+    if (theta_in && !theta) return -2;
+    const orc_config *cfg = &cfg_eff;
+    const int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q, N = nx * ny * nz;
+    const int64_t rows = (int64_t)cfg->batch * nz * ny;
+    int err = 0;
+#pragma omp parallel num_threads(g_threads)
+    {
+        node_fwd *s = (node_fwd *)malloc(sizeof(node_fwd));
+        if (!s) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(static)
+        for (int64_t r = 0; r < rows; ++r) {
+            if (!s) continue;
+            const int64_t b = r / (nz * ny), z = (r / ny) % nz, y = r % ny;
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t n = (z * ny + y) * nx + x;
+                for (int q = 0; q < Q; ++q) s->g[q] = g_in[(b * Q + q) * N + n];
+                body_force(cfg, (int)x, (int)y, (int)z, s->F);
+                double post[QMAX];
+                collide_node(cfg, &L, theta, s, post);
+                for (int q = 0; q < Q; ++q) post_out[(b * Q + q) * N + n] = post[q];
+            }
+        }
+        free(s);
+    }
+    free(owned);
+    return err;
 }
 
 /* Equilibrium initial state from a density and a velocity field:
@@ -593,7 +670,6 @@ static void collide_node_adjoint(const orc_config *cfg, const lattice_t *L, cons
     if (cfg->hidden > 0) {
         net_shape n;
         get_net(Q, cfg->hidden, cfg->net, &n);
-        int qt = cfg->quant;
         /* parameter offsets of every layer */
         int64_t off[NLMAX + 1];
         off[0] = 0;
@@ -611,10 +687,9 @@ static void collide_node_adjoint(const orc_config *cfg, const lattice_t *L, cons
                 db[o] += dz[o];
                 for (int i = 0; i < nin; ++i) dW[(int64_t)o * nin + i] += dz[o] * in[i];
             }
-            int scaled = !n.leaky && l + 1 < n.nl;
             for (int i = 0; i < nin; ++i) {
                 double d = 0.0;
-                for (int o = 0; o < nout; ++o) d += qweight(qt, scaled, W[(int64_t)o * nin + i]) * dz[o];
+                for (int o = 0; o < nout; ++o) d += qweight(cfg, W[(int64_t)o * nin + i]) * dz[o];
                 din[i] = d;
             }
             if (l > 0) {
@@ -630,43 +705,69 @@ static void collide_node_adjoint(const orc_config *cfg, const lattice_t *L, cons
 /* Adjoint of orc_step.  g_n: canonical state at step n; lam_n1 = dL/dg^{n+1};
  * writes lam_n = dL/dg^n and adds dL/dtheta into dtheta (may be NULL when
  * hidden == 0).  Streaming is a permutation, so its transpose reads
- * lam^{n+1}_q(x + c_q). */
-int orc_step_adjoint(const orc_config *cfg, const double *theta, const double *g_n,
+ * lam^{n+1}_q(x + c_q).  The parameter gradient of each thread's rows is
+ * summed separately and the partial sums are added in thread order. */
+int orc_step_adjoint(const orc_config *cfg_in, const double *theta_in, const double *g_n,
                      const double *lam_n1, double *lam_n, double *dtheta) {
     lattice_t L;
-    if (check_cfg(cfg, &L)) return -1;
-    if (cfg->collision != 0) return -3; /* the adjoint covers the fixed-tau collision only */
-    int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q, N = nx * ny * nz;
-    int64_t P = orc_param_elems(cfg->lattice, cfg->hidden, cfg->net);
-    double *scratch_dtheta = NULL;
-    if (cfg->hidden > 0 && !dtheta) {
-        scratch_dtheta = (double *)calloc((size_t)P, sizeof(double));
-        if (!scratch_dtheta) return -2;
-        dtheta = scratch_dtheta;
+    if (check_cfg(cfg_in, &L)) return -1;
+    if (cfg_in->collision != 0) return -3; /* the adjoint covers the fixed-tau collision only */
+    orc_config cfg_eff;
+    double *owned;
+    const double *theta = effective_theta(cfg_in, theta_in, &cfg_eff, &owned);
+    if (theta_in && !theta) return -2;
+    const orc_config *cfg = &cfg_eff;
+    const int64_t nx = cfg->nx, ny = cfg->ny, nz = cfg->nz, Q = L.Q, N = nx * ny * nz;
+    const int64_t rows = (int64_t)cfg->batch * nz * ny;
+    const int64_t P = cfg->hidden > 0 ? orc_param_elems(cfg->lattice, cfg->hidden, cfg->net) : 0;
+    const int nt = g_threads;
+    double *part = P > 0 ? (double *)calloc((size_t)(P * nt), sizeof(double)) : NULL;
+    if (P > 0 && !part) {
+        free(owned);
+        return -2;
     }
-    node_fwd *s = (node_fwd *)malloc(sizeof(node_fwd));
-    if (!s) { free(scratch_dtheta); return -2; }
-    for (int64_t b = 0; b < cfg->batch; ++b)
-        for (int64_t z = 0; z < nz; ++z)
-            for (int64_t y = 0; y < ny; ++y)
-                for (int64_t x = 0; x < nx; ++x) {
-                    int64_t n = (z * ny + y) * nx + x;
-                    double mu[QMAX], lam[QMAX];
-                    for (int q = 0; q < Q; ++q) {
-                        int64_t xd = wrap(x + L.c[q][0], nx);
-                        int64_t yd = wrap(y + L.c[q][1], ny);
-                        int64_t zd = wrap(z + L.c[q][2], nz);
-                        mu[q] = lam_n1[(b * Q + q) * N + (zd * ny + yd) * nx + xd];
-                        s->g[q] = g_n[(b * Q + q) * N + n];
-                        lam[q] = 0.0;
-                    }
-                    body_force(cfg, (int)x, (int)y, (int)z, s->F);
-                    collide_node_adjoint(cfg, &L, theta, s, mu, lam, dtheta);
-                    for (int q = 0; q < Q; ++q) lam_n[(b * Q + q) * N + n] = lam[q];
+    int err = 0;
+#pragma omp parallel num_threads(nt)
+    {
+#ifdef _OPENMP
+        const int tid = omp_get_thread_num();
+#else
+        const int tid = 0;
+#endif
+        double *dth = part ? part + (int64_t)tid * P : NULL;
+        node_fwd *s = (node_fwd *)malloc(sizeof(node_fwd));
+        if (!s) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(static)
+        for (int64_t r = 0; r < rows; ++r) {
+            if (!s) continue;
+            const int64_t b = r / (nz * ny), z = (r / ny) % nz, y = r % ny;
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t n = (z * ny + y) * nx + x;
+                double mu[QMAX], lam[QMAX];
+                for (int q = 0; q < Q; ++q) {
+                    int64_t xd = wrap(x + L.c[q][0], nx);
+                    int64_t yd = wrap(y + L.c[q][1], ny);
+                    int64_t zd = wrap(z + L.c[q][2], nz);
+                    mu[q] = lam_n1[(b * Q + q) * N + (zd * ny + yd) * nx + xd];
+                    s->g[q] = g_n[(b * Q + q) * N + n];
+                    lam[q] = 0.0;
                 }
-    free(s);
-    free(scratch_dtheta);
-    return 0;
+                body_force(cfg, (int)x, (int)y, (int)z, s->F);
+                collide_node_adjoint(cfg, &L, theta, s, mu, lam, dth);
+                for (int q = 0; q < Q; ++q) lam_n[(b * Q + q) * N + n] = lam[q];
+            }
+        }
+        free(s);
+    }
+    if (part && dtheta && !err)
+        for (int t = 0; t < nt; ++t)
+            for (int64_t i = 0; i < P; ++i) dtheta[i] += part[(int64_t)t * P + i];
+    free(part);
+    free(owned);
+    return err;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -892,6 +993,56 @@ int orc_mrt_moment_sums(const orc_config *cfg, const double *g_n, const double *
                         stats[i * 5 + 3] += mn * md;
                         stats[i * 5 + 4] += md * md;
                     }
+                }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Optimiser and coarse-graining of the training workloads                   */
+/* ------------------------------------------------------------------------ */
+
+/* One step of Adam with the weight decay added to the gradient as an L2
+ * term (the optimiser and the "weight decay rate" of Table S2), for n
+ * parameters, step count t >= 1 after this update:
+ *   g  = grad + wd p
+ *   m  = beta1 m + (1 - beta1) g
+ *   v  = beta2 v + (1 - beta2) g^2
+ *   p  = p - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps). */
+int orc_adam(int64_t n, double *p, const double *grad, double *m, double *v, double lr,
+             double beta1, double beta2, double eps, double wd, int t) {
+    if (n < 0 || t < 1) return -1;
+    double bc1 = 1.0 - pow(beta1, t), bc2 = 1.0 - pow(beta2, t);
+    for (int64_t i = 0; i < n; ++i) {
+        double g = grad[i] + wd * p[i];
+        m[i] = beta1 * m[i] + (1.0 - beta1) * g;
+        v[i] = beta2 * v[i] + (1.0 - beta2) * g * g;
+        double mhat = m[i] / bc1, vhat = v[i] / bc2;
+        p[i] -= lr * mhat / (sqrt(vhat) + eps);
+    }
+    return 0;
+}
+
+/* Block average of [batch][channels][nz][ny][nx] fields over factor^D fine
+ * nodes (D = 3 when nz > 1, else 2): the coarse-graining of the training
+ * data of the two-dimensional workload. */
+int orc_box_filter(int batch, int channels, int nx, int ny, int nz, int factor, const double *src,
+                   double *dst) {
+    if (batch < 1 || channels < 1 || nx < 1 || ny < 1 || nz < 1 || factor < 1) return -1;
+    int fz = nz > 1 ? factor : 1;
+    if (nx % factor || ny % factor || nz % fz) return -1;
+    int64_t cx = nx / factor, cy = ny / factor, cz = nz / fz;
+    double inv = 1.0 / ((double)factor * factor * fz);
+    for (int64_t p = 0; p < (int64_t)batch * channels; ++p)
+        for (int64_t z = 0; z < cz; ++z)
+            for (int64_t y = 0; y < cy; ++y)
+                for (int64_t x = 0; x < cx; ++x) {
+                    double acc = 0.0;
+                    for (int64_t dz = 0; dz < fz; ++dz)
+                        for (int64_t dy = 0; dy < factor; ++dy)
+                            for (int64_t dx = 0; dx < factor; ++dx)
+                                acc += src[((p * nz + z * fz + dz) * ny + y * factor + dy) * nx +
+                                           x * factor + dx];
+                    dst[((p * cz + z) * cy + y) * cx + x] = acc * inv;
                 }
     return 0;
 }

@@ -57,11 +57,14 @@ def _run(cmd, verbose):
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
-    for src, extra in SOURCES:
-        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
-        _run(compile_command(src, obj, extra), verbose)
-        objs.append(obj)
+    # the translation units compile in parallel (hipcc runs as a separate
+    # process; the threads only wait for it)
+    from concurrent.futures import ThreadPoolExecutor
+    objs = [os.path.join(CSRC, os.path.basename(src) + ".o") for src, _ in SOURCES]
+    jobs = [compile_command(src, obj, extra) for (src, extra), obj in zip(SOURCES, objs)]
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
+        for f in [ex.submit(_run, cmd, verbose) for cmd in jobs]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     for obj in objs:

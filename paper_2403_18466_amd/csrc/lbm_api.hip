@@ -35,9 +35,8 @@ struct lbm_ctx {
   // its adjoint: gather table and packed padded W, W^T and bias vectors
   int* wide_bidx;
   unsigned char* wide_bpacked;
-  // diagnostics partials, grown on demand
-  double* diag;
-  size_t diag_bytes;
+  // partial sums of the moment-space analysis (D3Q19 contexts)
+  double* mrt;
 };
 
 namespace {
@@ -520,8 +519,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   ctx->wide_nw = ctx->wide_nb = 0;
   ctx->wide_bidx = nullptr;
   ctx->wide_bpacked = nullptr;
-  ctx->diag = nullptr;
-  ctx->diag_bytes = 0;
+  ctx->mrt = nullptr;
   size_t bytes = sizeof(double) * 3 * (size_t)(MOM_BLOCKS > MOMENT_BLOCKS ? MOM_BLOCKS : MOMENT_BLOCKS) *
                  (size_t)cfg->batch;
   hipError_t e = hipMalloc(&ctx->partial, bytes);
@@ -529,6 +527,14 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     delete ctx;
     return fail(LBM_ERR_HIP, std::string("hipMalloc of the reduction buffer: ") +
                                  hipGetErrorString(e));
+  }
+  if (cfg->lattice == LBM_D3Q19) {
+    e = hipMalloc(&ctx->mrt, sizeof(double) * 19 * DIAG_BLOCKS * 5);
+    if (e != hipSuccess) {
+      lbm_destroy(ctx);
+      return fail(LBM_ERR_HIP, std::string("hipMalloc of the moment-analysis buffer: ") +
+                                   hipGetErrorString(e));
+    }
   }
   if (cfg->hidden != 0 && cfg->net == LBM_NET_LEAKY_300_300_100) {
     int pbytes = 0;
@@ -571,7 +577,7 @@ lbm_status lbm_destroy(lbm_ctx* ctx) {
   if (ctx->wide_packed) (void)hipFree(ctx->wide_packed);
   if (ctx->wide_bidx) (void)hipFree(ctx->wide_bidx);
   if (ctx->wide_bpacked) (void)hipFree(ctx->wide_bpacked);
-  if (ctx->diag) (void)hipFree(ctx->diag);
+  if (ctx->mrt) (void)hipFree(ctx->mrt);
   delete ctx;
   return LBM_OK;
   LBM_GUARD_END
@@ -867,25 +873,14 @@ lbm_status lbm_loss_population_sse(lbm_ctx* ctx, const float* A, const float* ta
   LBM_GUARD_END
 }
 
-namespace {
-// The context's diagnostics buffer of at least `bytes` (a reallocation waits
-// for the device).
-lbm_status diag_buffer(lbm_ctx* ctx, size_t bytes) {
-  if (ctx->diag_bytes >= bytes) return LBM_OK;
-  if (ctx->diag) {
-    LBM_HIP(hipDeviceSynchronize());
-    LBM_HIP(hipFree(ctx->diag));
-    ctx->diag = nullptr;
-    ctx->diag_bytes = 0;
-  }
-  LBM_HIP(hipMalloc(&ctx->diag, bytes));
-  ctx->diag_bytes = bytes;
-  return LBM_OK;
+size_t lbm_structure_functions_workspace_bytes(const lbm_ctx* ctx, int32_t lmax, int32_t pmax) {
+  if (!ctx || lmax < 1 || pmax < 1 || pmax > SF_PMAX) return 0;
+  return sizeof(double) * (size_t)lmax * DIAG_BLOCKS * 2 * (size_t)pmax;
 }
-}  // namespace
 
 lbm_status lbm_structure_functions(lbm_ctx* ctx, const float* u, int32_t lmax, int32_t pmax,
-                                   double* S, double* S_abs, hipStream_t stream) {
+                                   double* S, double* S_abs, void* ws, size_t ws_bytes,
+                                   hipStream_t stream) {
   LBM_GUARD_BEGIN
   lbm_status st = check_ctx(ctx);
   if (st != LBM_OK) return st;
@@ -895,18 +890,21 @@ lbm_status lbm_structure_functions(lbm_ctx* ctx, const float* u, int32_t lmax, i
   int lim = c.nx < c.ny ? c.nx : c.ny;
   if (c.lattice == LBM_D3Q19 && c.nz < lim) lim = c.nz;
   if (lmax < 1 || lmax > lim) return fail(LBM_ERR_INVALID, "lmax must be in 1..min(grid sizes)");
-  st = diag_buffer(ctx, sizeof(double) * (size_t)lmax * DIAG_BLOCKS * 2 * pmax);
-  if (st != LBM_OK) return st;
+  if (!ws) return fail(LBM_ERR_INVALID, "workspace is null");
+  if (ws_bytes < lbm_structure_functions_workspace_bytes(ctx, lmax, pmax))
+    return fail(LBM_ERR_WORKSPACE,
+                "workspace smaller than lbm_structure_functions_workspace_bytes()");
+  double* part = static_cast<double*>(ws);
   Grid G = grid_of(c);
   dim3 grid(DIAG_BLOCKS, (unsigned)lmax);
   if (c.lattice == LBM_D2Q9)
-    hipLaunchKernelGGL(structure_kernel<2>, grid, dim3(256), 0, stream, u, G, pmax, ctx->diag);
+    hipLaunchKernelGGL(structure_kernel<2>, grid, dim3(256), 0, stream, u, G, pmax, part);
   else
-    hipLaunchKernelGGL(structure_kernel<3>, grid, dim3(256), 0, stream, u, G, pmax, ctx->diag);
+    hipLaunchKernelGGL(structure_kernel<3>, grid, dim3(256), 0, stream, u, G, pmax, part);
   LBM_LAUNCHED("structure_kernel");
   const double count = (double)G.plane * G.batch * lattice_d(c.lattice);
   hipLaunchKernelGGL(structure_reduce_kernel, dim3(blocks_for((long long)lmax * 2 * pmax)), dim3(256),
-                     0, stream, ctx->diag, DIAG_BLOCKS, lmax, pmax, 1.0 / count, S, S_abs);
+                     0, stream, part, DIAG_BLOCKS, lmax, pmax, 1.0 / count, S, S_abs);
   LBM_LAUNCHED("structure_reduce_kernel");
   return LBM_OK;
   LBM_GUARD_END
@@ -920,13 +918,11 @@ lbm_status lbm_mrt_moment_sums(lbm_ctx* ctx, const float* A_n, const float* A_n1
   if (!A_n || !A_n1 || !stats) return fail(LBM_ERR_INVALID, "null array");
   if (ctx->cfg.lattice != LBM_D3Q19)
     return fail(LBM_ERR_UNSUPPORTED, "the moment matrix M is given for D3Q19 only");
-  st = diag_buffer(ctx, sizeof(double) * 19 * DIAG_BLOCKS * 5);
-  if (st != LBM_OK) return st;
   Grid G = grid_of(ctx->cfg);
   hipLaunchKernelGGL(mrt_sums_kernel, dim3(DIAG_BLOCKS, 19), dim3(256), 0, stream, A_n, A_n1, G,
-                     force_of(ctx->cfg), (float)ctx->cfg.rho0, ctx->diag);
+                     force_of(ctx->cfg), (float)ctx->cfg.rho0, ctx->mrt);
   LBM_LAUNCHED("mrt_sums_kernel");
-  hipLaunchKernelGGL(mrt_reduce_kernel, dim3(1), dim3(128), 0, stream, ctx->diag, DIAG_BLOCKS, stats);
+  hipLaunchKernelGGL(mrt_reduce_kernel, dim3(1), dim3(128), 0, stream, ctx->mrt, DIAG_BLOCKS, stats);
   LBM_LAUNCHED("mrt_reduce_kernel");
   return LBM_OK;
   LBM_GUARD_END

@@ -29,7 +29,9 @@ def structure_functions(L: "lbm.Lattice", A, lmax: int, pmax: int = 6):
     _, u, _ = L.moments(A)
     S = torch.empty((pmax, lmax), dtype=torch.float64, device=L.device)
     Sa = torch.empty_like(S)
-    lbm.lbm_structure_functions(L.ctx, L.cfg, u, lmax, pmax, S, Sa)
+    nws = lbm.lbm_structure_functions_workspace_bytes(L.ctx, lmax, pmax)
+    ws = torch.empty(nws // 8 + 1, dtype=torch.float64, device=L.device)
+    lbm.lbm_structure_functions(L.ctx, L.cfg, u, lmax, pmax, S, Sa, ws)
     return S.cpu().numpy(), Sa.cpu().numpy()
 
 

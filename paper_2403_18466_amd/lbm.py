@@ -34,8 +34,8 @@ EXPORTS = (
     "lbm_create", "lbm_destroy", "lbm_state_elems", "lbm_param_elems", "lbm_workspace_bytes",
     "lbm_lattice_tables", "lbm_init", "lbm_step", "lbm_moments", "lbm_shift",
     "lbm_step_backward", "lbm_step_backward_seq", "lbm_loss_velocity_mse", "lbm_adam", "lbm_box_filter",
-    "lbm_subsample", "lbm_loss_population_sse", "lbm_structure_functions",
-    "lbm_mrt_moment_sums", "lbm_status_str", "lbm_last_error",
+    "lbm_subsample", "lbm_loss_population_sse", "lbm_structure_functions_workspace_bytes",
+    "lbm_structure_functions", "lbm_mrt_moment_sums", "lbm_status_str", "lbm_last_error",
 )
 
 
@@ -89,7 +89,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_box_filter": ([vp, vp, i32, i32, i32, i32, i32, i32, vp], ctypes.c_int),
         "lbm_subsample": ([i32, vp, vp, i32, i32, i32, i32, i32, vp], ctypes.c_int),
         "lbm_loss_population_sse": ([vp, vp, vp, vp, i32, vp, vp, vp], ctypes.c_int),
-        "lbm_structure_functions": ([vp, vp, i32, i32, vp, vp, vp], ctypes.c_int),
+        "lbm_structure_functions_workspace_bytes": ([vp, i32, i32], sz),
+        "lbm_structure_functions": ([vp, vp, i32, i32, vp, vp, vp, sz, vp], ctypes.c_int),
         "lbm_mrt_moment_sums": ([vp, vp, vp, vp, vp], ctypes.c_int),
         "lbm_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "lbm_last_error": ([], ctypes.c_char_p),
@@ -339,11 +340,18 @@ def lbm_loss_population_sse(ctx, cfg: Config, A, target, nodes, loss, dLdA=None,
         "lbm_loss_population_sse")
 
 
-def lbm_structure_functions(ctx, cfg: Config, u, lmax, pmax, S, S_abs, stream=None):
+def lbm_structure_functions_workspace_bytes(ctx, lmax, pmax) -> int:
+    return int(load_library().lbm_structure_functions_workspace_bytes(ctx, int(lmax), int(pmax)))
+
+
+def lbm_structure_functions(ctx, cfg: Config, u, lmax, pmax, S, S_abs, ws, stream=None):
     n = cfg.batch * cfg.D * cfg.nx * cfg.ny * cfg.nz
+    if ws is None or ws.device.type != "cuda" or not ws.is_contiguous():
+        raise ValueError("ws must be a contiguous device tensor")
     _check(load_library().lbm_structure_functions(
         ctx, _ptr(u, torch.float32, n, "u"), int(lmax), int(pmax),
         _ptr(S, torch.float64, lmax * pmax, "S"), _ptr(S_abs, torch.float64, lmax * pmax, "S_abs"),
+        ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
         _stream(stream)), "lbm_structure_functions")
 
 

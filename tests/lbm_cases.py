@@ -68,3 +68,77 @@ def random_state(ocfg, seed, scale=0.02):
 def params(Q, H, seed, kind="glorot"):
     p = inputs.glorot_params(Q, H, seed) if kind == "glorot" else inputs.random_params(Q, H, seed)
     return p.astype(np.float32)
+
+
+# float32 value of c = 2 log2(e): the 16-bit tanh kernels evaluate
+# tanh z = 1 - 2 / (1 + 2^(c z)) and carry c in the operands of the two tanh
+# layers (a documented implementation choice of those kernels)
+TANH_ARG_SCALE = np.float32(2.8853900817779268)
+
+
+def _round16(a, prec):
+    """float32 values rounded once to bf16 / fp16 (round to nearest even)."""
+    import torch
+    dt = torch.bfloat16 if prec == "bf16" else torch.float16
+    t = torch.from_numpy(np.ascontiguousarray(a, np.float32))
+    return t.to(dt).to(torch.float64).numpy()
+
+
+def kernel_operand_theta(theta, Q, H, prec, net="tanh"):
+    """The parameters the 16-bit kernels compute with, in effect, as float64.
+
+    Tanh network: the operands of layers 1 and 2 hold fl32(c w) rounded to
+    the format and the layer-1 bias enters as one more operand column, so
+    these layers compute c z with weights round(fl32(c w)) / c; b2 is held
+    as fl32(c b2).  Layer 3 rounds its weights as they are; b3 stays float32.
+    The SI's network (LeakyReLU) rounds every weight and, as an operand
+    column, b1.  Passed to the oracle with quant_weights=False (activation
+    rounding only), this reproduces the kernels' rounding, which the tight
+    parity bars check; the A19 emulation (every weight rounded as it is,
+    biases exact) is the independent reference of the accuracy bars."""
+    th = np.asarray(theta, np.float32)
+    if prec not in ("bf16", "fp16"):
+        return th.astype(np.float64)
+    out = th.astype(np.float64).copy()
+    if net == "tanh":
+        c = TANH_ARG_SCALE
+        cd = float(c)
+        oW1, ob1 = 0, H * Q
+        oW2, ob2 = ob1 + H, ob1 + H + H * H
+        oW3 = ob2 + H
+        out[oW1:ob1] = _round16(c * th[oW1:ob1], prec) / cd
+        out[ob1:oW2] = _round16(c * th[ob1:oW2], prec) / cd
+        out[oW2:ob2] = _round16(c * th[oW2:ob2], prec) / cd
+        out[ob2:oW3] = (c * th[ob2:oW3]).astype(np.float64) / cd
+        out[oW3:oW3 + Q * H] = _round16(th[oW3:oW3 + Q * H], prec)
+        return out
+    widths = [Q, 300, 300, 100, Q]
+    o = 0
+    for l in range(4):
+        nw = widths[l + 1] * widths[l]
+        out[o:o + nw] = _round16(th[o:o + nw], prec)
+        if l == 0:
+            out[o + nw:o + nw + widths[1]] = _round16(th[o + nw:o + nw + widths[1]], prec)
+        o += nw + widths[l + 1]
+    return out
+
+
+def kernel_emulation(ocfg, theta, prec):
+    """(oracle config, theta) reproducing the 16-bit kernels' rounding; see
+    kernel_operand_theta."""
+    import dataclasses
+    cfg = dataclasses.replace(ocfg, quant=prec, quant_weights=False)
+    return cfg, kernel_operand_theta(theta, ocfg.Q, ocfg.hidden, prec, ocfg.net)
+
+
+def a19_config(ocfg, prec):
+    """The oracle's emulation of the reduced-precision network at the
+    rounding points of the precision plan: input, every weight and every
+    hidden activation rounded; biases and sums exact."""
+    import dataclasses
+    return dataclasses.replace(ocfg, quant=prec, quant_weights=True)
+
+
+def exact_config(ocfg):
+    import dataclasses
+    return dataclasses.replace(ocfg, quant="none", quant_weights=True)

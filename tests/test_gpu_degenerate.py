@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 
 import oracle
-from lbm_cases import lib_config, params, random_state, rel_l2, to_canonical, to_shifted
+from lbm_cases import (a19_config, kernel_emulation, lib_config, params, random_state, rel_l2,
+                       to_canonical, to_shifted)
 from paper_2403_18466_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -67,13 +68,15 @@ def test_tanh_network(lbm, lat, shape):
     assert rel_l2(got, want) < 1e-5
     # bf16 operands: one step against the emulated rounding, within the
     # bars of the full-size tests
-    oq = oracle.Config(lattice=lat, nx=nx, ny=ny, nz=nz, batch=2, tau=0.55, hidden=64,
-                       out_scale=0.25, quant="bf16")
-    emu = oracle.step(oq, g0, theta.astype(np.float64))
+    kcfg, kth = kernel_emulation(ocfg, theta, "bf16")
+    emu = oracle.step(kcfg, g0, kth)
+    a19 = oracle.step(a19_config(ocfg, "bf16"), g0, theta.astype(np.float64))
     exact = oracle.step(ocfg, g0, theta.astype(np.float64))
-    got = run_gpu(lbm, oq, g0, theta, 1, prec="bf16")
+    got = run_gpu(lbm, ocfg, g0, theta, 1, prec="bf16")
     upd = np.abs(exact - g0).max()
     assert np.abs(got - emu).max() / upd < 2e-3
+    assert np.abs(got - a19).max() / upd < 5e-3
+    assert np.abs(got - exact).max() / upd < 5e-3
 
 
 @pytest.mark.parametrize("lat,shape", SHAPES)

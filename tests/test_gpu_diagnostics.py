@@ -31,10 +31,26 @@ def test_structure_functions(lbm, lat, shape):
     L = lbm.Lattice(lib_config(ocfg))
     S = torch.empty((pmax, lmax), dtype=torch.float64, device="cuda")
     Sa = torch.empty_like(S)
-    lbm.lbm_structure_functions(L.ctx, L.cfg, torch.from_numpy(u).cuda(), lmax, pmax, S, Sa)
+    nws = lbm.lbm_structure_functions_workspace_bytes(L.ctx, lmax, pmax)
+    assert nws == 8 * lmax * 64 * 2 * pmax
+    ud = torch.from_numpy(u).cuda()
+    # a workspace one double short is refused before anything is launched
+    short = torch.empty(nws // 8 - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_structure_functions(L.ctx, L.cfg, ud, lmax, pmax, S, Sa, short)
+    assert e.value.status == lbm.LBM_ERR_WORKSPACE
+    ws = torch.empty(nws // 8, dtype=torch.float64, device="cuda")
+    lbm.lbm_structure_functions(L.ctx, L.cfg, ud, lmax, pmax, S, Sa, ws)
     got, gabs = S.cpu().numpy(), Sa.cpu().numpy()
     assert np.abs(got - want).max() <= 1e-12 * np.abs(wabs).max(axis=1, keepdims=True).max()
     assert np.all(np.abs(gabs - wabs) <= 1e-12 * wabs)
+    # a smaller second call in the same workspace
+    want2, wabs2 = oracle.structure_functions(ocfg, u.astype(np.float64), 3, 2)
+    S2 = torch.empty((2, 3), dtype=torch.float64, device="cuda")
+    Sa2 = torch.empty_like(S2)
+    lbm.lbm_structure_functions(L.ctx, L.cfg, ud, 3, 2, S2, Sa2, ws)
+    assert np.all(np.abs(Sa2.cpu().numpy() - wabs2) <= 1e-12 * wabs2)
+    assert np.abs(S2.cpu().numpy() - want2).max() <= 1e-12 * np.abs(wabs2).max()
     L.close()
 
 

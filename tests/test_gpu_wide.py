@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 import oracle
-from lbm_cases import lib_config, random_state, rel_l2, to_canonical, to_shifted
+from lbm_cases import (a19_config, kernel_emulation, lib_config, random_state, rel_l2, to_canonical,
+                       to_shifted)
 from paper_2403_18466_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -93,21 +94,25 @@ def test_wide_reduced_precision(lbm, prec, lat, shape):
     nz, ny, nx = shape
     base = dict(lattice=lat, nx=nx, ny=ny, nz=nz, batch=1, tau=0.51, hidden=300, net="paper",
                 out_scale=0.5)
-    ocfg_q = oracle.Config(quant=prec, **base)
     ocfg_x = oracle.Config(**base)
-    theta = inputs.glorot_params_net(inputs.net_widths(ocfg_q.Q, 0, "paper"), seed=1)
-    g0 = random_state(ocfg_q, 52, scale=0.05)
-    got = run_gpu(lbm, ocfg_q, g0, theta, 1, prec=prec)
-    emu = oracle.step(ocfg_q, g0, theta.astype(np.float64))
+    theta = inputs.glorot_params_net(inputs.net_widths(ocfg_x.Q, 0, "paper"), seed=1)
+    g0 = random_state(ocfg_x, 52, scale=0.05)
+    got = run_gpu(lbm, ocfg_x, g0, theta, 1, prec=prec)
+    kcfg, kth = kernel_emulation(ocfg_x, theta, prec)
+    emu = oracle.step(kcfg, g0, kth)
+    a19 = oracle.step(a19_config(ocfg_x, prec), g0, theta.astype(np.float64))
     exact = oracle.step(ocfg_x, g0, theta.astype(np.float64))
     upd = np.abs(exact - g0).max()
     l2_emu = np.linalg.norm(got - emu)
     l2_round = np.linalg.norm(emu - exact)
+    vs_exact = np.linalg.norm(got - exact) / np.linalg.norm(a19 - exact)
     max_emu = np.abs(got - emu).max() / upd
     max_exact = np.abs(got - exact).max() / upd
     print(f"{prec} {lat}: L2 |gpu-emulated| / L2 |emulated-fp64| = {l2_emu / l2_round:.3f}; "
+          f"L2 |gpu-fp64| / L2 |A19-fp64| = {vs_exact:.3f}; "
           f"max |gpu-emulated| {max_emu:.2e}, max |gpu-fp64| {max_exact:.2e} of max |update|")
     assert l2_emu < 0.25 * l2_round
+    assert vs_exact < 1.5
     assert max_emu < (2e-3 if prec == "bf16" else 5e-4)
     assert max_exact < (1e-2 if prec == "bf16" else 2e-3)
 
@@ -161,13 +166,13 @@ def test_wide_one_step_sampled(lbm, lat, n):
     zs, ys, xs = (np.array([p[i] for p in pts]) for i in range(3))
     got = out[0].cpu().numpy()[:, zs, ys, xs].astype(np.float64)
     kw = dict(lattice=lat, nx=1, ny=1, nz=1, tau=0.51, hidden=300, net="paper", out_scale=2.0 ** -6)
-    one_q = oracle.Config(quant="bf16", **kw)
     one_x = oracle.Config(**kw)
+    one_q, kth = kernel_emulation(one_x, theta, "bf16")
     th64 = theta.astype(np.float64)
     want, exact, pre = [], [], []
     for z, y, x in pts:
         gg = g32[0, :, z, y, x].astype(np.float64).reshape(1, Q, 1, 1, 1)
-        want.append(oracle.collide(one_q, gg, th64)[0, :, 0, 0, 0])
+        want.append(oracle.collide(one_q, gg, kth)[0, :, 0, 0, 0])
         exact.append(oracle.collide(one_x, gg, th64)[0, :, 0, 0, 0])
         pre.append(gg[0, :, 0, 0, 0])
     want, exact, pre = np.array(want).T, np.array(exact).T, np.array(pre).T
@@ -235,11 +240,12 @@ def test_wide_adjoint_reduced_precision(lbm, prec):
     GPU also rounds its backward operands (dY, dZ), so the bounds are
     stated, as for the small network."""
     ocfg = oracle.Config(lattice="D3Q19", nx=9, ny=6, nz=5, batch=1, tau=0.51, hidden=300,
-                         net="paper", out_scale=0.25, quant=prec)
+                         net="paper", out_scale=0.25)
     theta = inputs.glorot_params_net(inputs.net_widths(19, 0, "paper"), seed=1)
     g = random_state(ocfg, 57, scale=0.03)
     lam1 = random_state(ocfg, 58, scale=1.0)
-    want, wdth = oracle.step_adjoint(ocfg, g, lam1, theta.astype(np.float64))
+    kcfg, kth = kernel_emulation(ocfg, theta, prec)
+    want, wdth = oracle.step_adjoint(kcfg, g, lam1, kth)
     got, gdth = gpu_adjoint(lbm, ocfg, g, lam1, theta, prec=prec)
     e_lam, e_th = rel_l2(got, want), rel_l2(gdth, wdth)
     print(f"{prec}: lam rel L2 {e_lam:.2e}, dtheta rel L2 {e_th:.2e}")
@@ -252,11 +258,12 @@ def test_wide_adjoint_4335_nodes(lbm):
     last one ragged) against the oracle's emulated-rounding adjoint, every
     parameter block on its own."""
     ocfg = oracle.Config(lattice="D3Q19", nx=17, ny=17, nz=15, batch=1, tau=0.51, hidden=300,
-                         net="paper", out_scale=0.25, quant="bf16")
+                         net="paper", out_scale=0.25)
     theta = inputs.glorot_params_net(inputs.net_widths(19, 0, "paper"), seed=1)
     g = random_state(ocfg, 57, scale=0.03)
     lam1 = random_state(ocfg, 58, scale=1.0)
-    want, wdth = oracle.step_adjoint(ocfg, g, lam1, theta.astype(np.float64))
+    kcfg, kth = kernel_emulation(ocfg, theta, "bf16")
+    want, wdth = oracle.step_adjoint(kcfg, g, lam1, kth)
     got, gdth = gpu_adjoint(lbm, ocfg, g, lam1, theta, prec="bf16")
     e_lam, e_th = rel_l2(got, want), rel_l2(gdth, wdth)
     offs = _blocks(ocfg.Q)

@@ -582,9 +582,8 @@ def test_velocity_mse_loss_definition():
 # --------------------------------------------------------------------------
 # P14: emulated reduced-precision network.  The same collision written as
 # matrix products with torch's own float32 -> bfloat16 / float16 conversions
-# at the stated rounding points (input, both hidden activations, weights and
-# the layer-1 bias, which the network reads as one more input column; the
-# tanh layers' operands are the float32 products c W, c = 2 log2 e).
+# at the stated rounding points: the input, both hidden activations and every
+# weight; the biases and all sums stay exact.
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("quant", ["bf16", "fp16"])
@@ -620,20 +619,24 @@ def test_emulated_quantisation_points(quant):
     b2 = theta[o:o + H]; o += H
     W3 = theta[o:o + 9 * H].reshape(9, H); o += 9 * H
     b3 = theta[o:o + 9]
-    # the tanh layers hold c W in the operand: float32 product, then rounded
-    c = float(np.float32(2.8853900817779268))
-
-    def rnd_scaled(a):
-        return rnd((np.float32(c) * np.asarray(a, np.float32)).astype(np.float64)) / c
-
     x0 = rnd_act(g.reshape(9, -1))
-    h1 = rnd_act(np.tanh(rnd_scaled(W1) @ x0 + rnd_scaled(b1)[:, None]))
-    h2 = rnd_act(np.tanh(rnd_scaled(W2) @ h1 + b2[:, None]))
+    h1 = rnd_act(np.tanh(rnd(W1) @ x0 + b1[:, None]))
+    h2 = rnd_act(np.tanh(rnd(W2) @ h1 + b2[:, None]))
     y = rnd(W3) @ h2 + b3[:, None]
     P = brute.projector()
     want = (oracle.collide(cfg_0, g).reshape(9, -1) + P @ ((s / tau) * y)).reshape(g.shape)
     got = oracle.collide(cfg_q, g, theta)
     assert np.abs(got - want).max() < 1e-14
-    # and the rounding is visible: the exact network gives a different result
+    # with the weights taken as given, only the input and the activations round
+    cfg_a = oracle.Config(nx=n, ny=n, tau=tau, hidden=H, out_scale=s, quant=quant,
+                          quant_weights=False)
+    h1 = rnd_act(np.tanh(W1 @ x0 + b1[:, None]))
+    h2 = rnd_act(np.tanh(W2 @ h1 + b2[:, None]))
+    y = W3 @ h2 + b3[:, None]
+    want_a = (oracle.collide(cfg_0, g).reshape(9, -1) + P @ ((s / tau) * y)).reshape(g.shape)
+    assert np.abs(oracle.collide(cfg_a, g, theta) - want_a).max() < 1e-14
+    # passing the rounded weights in that mode is the full emulation
+    th_r = np.concatenate([rnd(W1).ravel(), b1, rnd(W2).ravel(), b2, rnd(W3).ravel(), b3])
+    assert np.abs(oracle.collide(cfg_a, g, th_r) - got).max() < 1e-15
     exact = oracle.collide(oracle.Config(nx=n, ny=n, tau=tau, hidden=H, out_scale=s), g, theta)
     assert np.abs(exact - got).max() > 1e-5
