@@ -89,12 +89,15 @@ static __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p,
                                                    const float* __restrict__ grad,
                                                    float* __restrict__ m, float* __restrict__ v,
                                                    long long n, float lr, float b1, float b2,
-                                                   float eps, float wd, float bc1, float bc2) {
+                                                   float omb1, float omb2, float eps, float wd,
+                                                   float bc1, float bc2) {
+  // omb1 = 1 - b1 and omb2 = 1 - b2 come from the host in float64: formed
+  // here from the float32 betas, 1 - 0.999f would be off by 1.3e-5
   long long i = blockIdx.x * 256LL + threadIdx.x;
   if (i >= n) return;
   float g = grad[i] + wd * p[i];
-  float mi = b1 * m[i] + (1.f - b1) * g;
-  float vi = b2 * v[i] + (1.f - b2) * g * g;
+  float mi = b1 * m[i] + omb1 * g;
+  float vi = b2 * v[i] + omb2 * g * g;
   m[i] = mi;
   v[i] = vi;
   p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);

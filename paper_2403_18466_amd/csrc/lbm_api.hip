@@ -795,8 +795,8 @@ lbm_status lbm_adam(float* param, const float* grad, float* m, float* v, int64_t
   if (n == 0) return LBM_OK;
   float bc1 = (float)(1.0 - std::pow(beta1, t)), bc2 = (float)(1.0 - std::pow(beta2, t));
   hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, param, grad, m, v,
-                     (long long)n, (float)lr, (float)beta1, (float)beta2, (float)eps,
-                     (float)weight_decay, bc1, bc2);
+                     (long long)n, (float)lr, (float)beta1, (float)beta2, (float)(1.0 - beta1),
+                     (float)(1.0 - beta2), (float)eps, (float)weight_decay, bc1, bc2);
   LBM_LAUNCHED("adam_kernel");
   return LBM_OK;
   LBM_GUARD_END

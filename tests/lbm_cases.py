@@ -94,7 +94,7 @@ def kernel_operand_theta(theta, Q, H, prec, net="tanh"):
     The SI's network (LeakyReLU) rounds every weight and, as an operand
     column, b1.  Passed to the oracle with quant_weights=False (activation
     rounding only), this reproduces the kernels' rounding, which the tight
-    parity bars check; the A19 emulation (every weight rounded as it is,
+    parity bars check; the plain-rounding emulation (every weight rounded as it is,
     biases exact) is the independent reference of the accuracy bars."""
     th = np.asarray(theta, np.float32)
     if prec not in ("bf16", "fp16"):
@@ -131,7 +131,7 @@ def kernel_emulation(ocfg, theta, prec):
     return cfg, kernel_operand_theta(theta, ocfg.Q, ocfg.hidden, prec, ocfg.net)
 
 
-def a19_config(ocfg, prec):
+def plain_rounding_config(ocfg, prec):
     """The oracle's emulation of the reduced-precision network at the
     rounding points of the precision plan: input, every weight and every
     hidden activation rounded; biases and sums exact."""

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from lbm_cases import (a19_config, kernel_emulation, lib_config, params, random_state, rel_l2,
+from lbm_cases import (plain_rounding_config, kernel_emulation, lib_config, params, random_state, rel_l2,
                        to_canonical, to_shifted)
 from paper_2403_18466_amd import inputs
 
@@ -70,12 +70,12 @@ def test_tanh_network(lbm, lat, shape):
     # bars of the full-size tests
     kcfg, kth = kernel_emulation(ocfg, theta, "bf16")
     emu = oracle.step(kcfg, g0, kth)
-    a19 = oracle.step(a19_config(ocfg, "bf16"), g0, theta.astype(np.float64))
+    plain = oracle.step(plain_rounding_config(ocfg, "bf16"), g0, theta.astype(np.float64))
     exact = oracle.step(ocfg, g0, theta.astype(np.float64))
     got = run_gpu(lbm, ocfg, g0, theta, 1, prec="bf16")
     upd = np.abs(exact - g0).max()
     assert np.abs(got - emu).max() / upd < 2e-3
-    assert np.abs(got - a19).max() / upd < 5e-3
+    assert np.abs(got - plain).max() / upd < 5e-3
     assert np.abs(got - exact).max() / upd < 5e-3
 
 

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
-from lbm_cases import (a19_config, exact_config, fourier_state, kernel_emulation, lib_config,
+from lbm_cases import (plain_rounding_config, exact_config, fourier_state, kernel_emulation, lib_config,
                        params, random_state, rel_l2, to_canonical, to_shifted)
 
 torch = pytest.importorskip("torch")
@@ -199,10 +199,10 @@ def test_nlbm_reduced_precision(lbm, prec, lat, shape, H):
     difference moves an activation across a rounding boundary: the L2 gap is
     a small fraction of the rounding effect.
 
-    Accuracy (independent of the kernel's scheme): against the oracle's A19
+    Accuracy (independent of the kernel's scheme): against the oracle's plain rounding
     emulation (input, weights, activations rounded as they are) and against
     plain fp64.  The kernel's error against fp64 must be of the size of the
-    A19 scheme's own error, and its distance from the A19 result within the
+    plain-rounding scheme's own error, and its distance from the plain rounding result within the
     bound stated here."""
     nz, ny, nx = shape
     base = oracle.Config(lattice=lat, nx=nx, ny=ny, nz=nz, batch=1, tau=0.51, hidden=H,
@@ -212,22 +212,22 @@ def test_nlbm_reduced_precision(lbm, prec, lat, shape, H):
     got = run_gpu(lbm, base, g0, theta, 1, prec=prec)
     kcfg, kth = kernel_emulation(base, theta, prec)
     emu = oracle.step(kcfg, g0, kth)
-    a19 = oracle.step(a19_config(base, prec), g0, theta.astype(np.float64))
+    plain = oracle.step(plain_rounding_config(base, prec), g0, theta.astype(np.float64))
     exact = oracle.step(exact_config(base), g0, theta.astype(np.float64))
     upd = np.abs(exact - g0).max()
-    r_a19 = np.linalg.norm(a19 - exact)
+    r_plain = np.linalg.norm(plain - exact)
     tight = np.linalg.norm(got - emu) / np.linalg.norm(emu - exact)
-    vs_a19 = np.linalg.norm(got - a19) / r_a19
-    vs_exact = np.linalg.norm(got - exact) / r_a19
+    vs_plain = np.linalg.norm(got - plain) / r_plain
+    vs_exact = np.linalg.norm(got - exact) / r_plain
     max_emu = np.abs(got - emu).max() / upd
-    max_a19 = np.abs(got - a19).max() / upd
+    max_plain = np.abs(got - plain).max() / upd
     max_exact = np.abs(got - exact).max() / upd
     print(f"{prec} {lat} H={H}: L2 gap / L2 rounding effect: kernel scheme {tight:.3f}; "
-          f"|gpu-A19| {vs_a19:.3f}, |gpu-fp64| {vs_exact:.3f} of |A19-fp64|; max of max|update|: "
-          f"kernel scheme {max_emu:.2e}, A19 {max_a19:.2e}, fp64 {max_exact:.2e}")
+          f"|gpu-plain| {vs_plain:.3f}, |gpu-fp64| {vs_exact:.3f} of |plain-fp64|; max of max|update|: "
+          f"kernel scheme {max_emu:.2e}, plain rounding {max_plain:.2e}, fp64 {max_exact:.2e}")
     assert tight < 0.25
     assert max_emu < (2e-3 if prec == "bf16" else 5e-4)
     assert vs_exact < 1.5
-    assert vs_a19 < 2.0
-    assert max_a19 < (5e-3 if prec == "bf16" else 1e-3)
+    assert vs_plain < 2.0
+    assert max_plain < (5e-3 if prec == "bf16" else 1e-3)
     assert max_exact < (5e-3 if prec == "bf16" else 1e-3)
