@@ -232,6 +232,27 @@ lbm_status lbm_step_backward(lbm_ctx* ctx, const float* A_n, const float* theta,
                              const float* lam_n1, float* lam_n, float* dtheta, void* ws,
                              size_t ws_bytes, hipStream_t stream);
 
+/* lbm_step_backward without a workspace argument and without any
+ * allocation, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc).  The per-workgroup partial gradients go to a static device
+ * buffer of 8 MiB that the library holds on each device until the process
+ * ends (looked up by lbm_create); every partial row is written before it is
+ * read, so nothing needs clearing between calls.  Configurations whose
+ * lbm_workspace_bytes() exceeds 8 MiB return LBM_ERR_WORKSPACE with nothing
+ * enqueued: this covers plain BGK and every tanh network on grids of any
+ * size (their partials depend only on the number of compute units and
+ * parameters: 6.8 MB at most on 256 compute units), and the SI's network,
+ * whose workspace holds every activation of every node (about 6 KB per node
+ * in bf16), only on grids of up to about a thousand nodes.  All calls on one
+ * device share the buffer: calls that may overlap on one device (different
+ * streams, or host threads) race and must be ordered by the caller.
+ * Arguments, results and other errors as lbm_step_backward, which it
+ * equals bit for bit. */
+lbm_status lbm_step_backward_static(lbm_ctx* ctx, const float* A_n, const float* theta,
+                                    const float* lam_n1, float* lam_n, float* dtheta,
+                                    hipStream_t stream);
+
 /* The adjoint of nsteps consecutive lbm_step calls, the backward pass over
  * one checkpoint segment of the SI's unrolled training: for m = nsteps - 1
  * down to 0, lbm_step_backward with A_n = A[m], giving

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -22,10 +23,19 @@
 
 using namespace lbm;
 
+// Scratch of lbm_step_backward_static: the adjoint's per-workgroup partial
+// parameter gradients, in memory the library holds on every device it runs
+// on until the process ends.  Host code never uses this name as a device
+// address: lbm_create looks up each device's address of it once, with the
+// device current, and the calls pass that address to the kernels.
+constexpr size_t kStaticScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 struct lbm_ctx {
   lbm_config cfg;
   int device;
   int ncu;
+  void* scratch;  // this device's address of `scratch` (null if the lookup failed)
   double* partial;  // float64 reduction partials, [batch][max(MOM_BLOCKS, MOMENT_BLOCKS)][3]
   // LBM_NET_LEAKY_300_300_100: theta -> fragment-order gather table and the
   // packed weights it fills
@@ -239,6 +249,30 @@ lbm_status check_ctx(const lbm_ctx* ctx) {
   if (dev != ctx->device)
     return fail(LBM_ERR_INVALID, "current device differs from the context's device");
   return LBM_OK;
+}
+
+// Device address of `scratch` on device dev (current), looked up once per
+// device.  On failure the error is recorded and cleared, and null returned.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices];
+std::string g_scratch_err[kMaxDevices];
+
+void* static_scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev] && g_scratch_err[dev].empty()) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      g_scratch_err[dev] = std::string("hipGetSymbolAddress of the static scratch: ") +
+                           hipGetErrorString(e);
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_addr[dev] = p;
+  }
+  return g_scratch_addr[dev];
 }
 
 unsigned blocks_for(long long n, int per_block = 256) {
@@ -513,6 +547,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   ctx->cfg = *cfg;
   ctx->device = dev;
   ctx->ncu = prop.multiProcessorCount;
+  ctx->scratch = static_scratch_address(dev);
   ctx->partial = nullptr;
   ctx->wide_idx = nullptr;
   ctx->wide_packed = nullptr;
@@ -721,6 +756,30 @@ lbm_status lbm_step_backward(lbm_ctx* ctx, const float* A_n, const float* theta,
   if (ctx->cfg.lattice == LBM_D2Q9)
     return run_backward<D2Q9>(ctx, A_n, theta, lam_n1, lam_n, dtheta, ws, stream);
   return run_backward<D3Q19>(ctx, A_n, theta, lam_n1, lam_n, dtheta, ws, stream);
+  LBM_GUARD_END
+}
+
+lbm_status lbm_step_backward_static(lbm_ctx* ctx, const float* A_n, const float* theta,
+                                    const float* lam_n1, float* lam_n, float* dtheta,
+                                    hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  lbm_status st = check_ctx(ctx);
+  if (st != LBM_OK) return st;
+  const size_t need = lbm_workspace_bytes(ctx);
+  if (need > kStaticScratchBytes)
+    return fail(LBM_ERR_WORKSPACE,
+                "this configuration needs " + std::to_string(need) +
+                    " bytes of adjoint scratch; the static buffer holds " +
+                    std::to_string(kStaticScratchBytes) +
+                    " (use lbm_step_backward with a workspace)");
+  if (!ctx->scratch) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    const bool in_range = ctx->device >= 0 && ctx->device < kMaxDevices;
+    return fail(LBM_ERR_HIP, in_range ? g_scratch_err[ctx->device]
+                                      : std::string("device index out of range"));
+  }
+  return lbm_step_backward(ctx, A_n, theta, lam_n1, lam_n, dtheta, ctx->scratch,
+                           kStaticScratchBytes, stream);
   LBM_GUARD_END
 }
 

@@ -33,7 +33,7 @@ COLLISIONS = {"bgk": LBM_COLLISION_BGK, "smagorinsky": LBM_COLLISION_SMAGORINSKY
 EXPORTS = (
     "lbm_create", "lbm_destroy", "lbm_state_elems", "lbm_param_elems", "lbm_workspace_bytes",
     "lbm_lattice_tables", "lbm_init", "lbm_step", "lbm_moments", "lbm_shift",
-    "lbm_step_backward", "lbm_step_backward_seq", "lbm_loss_velocity_mse", "lbm_adam", "lbm_box_filter",
+    "lbm_step_backward", "lbm_step_backward_static", "lbm_step_backward_seq", "lbm_loss_velocity_mse", "lbm_adam", "lbm_box_filter",
     "lbm_subsample", "lbm_loss_population_sse", "lbm_structure_functions_workspace_bytes",
     "lbm_structure_functions", "lbm_mrt_moment_sums", "lbm_status_str", "lbm_last_error",
 )
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_moments": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "lbm_shift": ([vp, vp, vp, i32, vp], ctypes.c_int),
         "lbm_step_backward": ([vp, vp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "lbm_step_backward_static": ([vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "lbm_step_backward_seq": ([vp, vp, i32, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
         "lbm_loss_velocity_mse": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "lbm_adam": ([vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, dbl, i32, vp], ctypes.c_int),
@@ -263,6 +264,19 @@ def lbm_step_backward(ctx, cfg: Config, A_n, theta, lam_n1, lam_n, dtheta, ws, s
         _ptr(dtheta, torch.float32, npar, "dtheta", allow_none=cfg.hidden == 0),
         None if ws is None else ctypes.c_void_p(ws.data_ptr()), ws_bytes,
         _stream(stream)), "lbm_step_backward")
+
+
+def lbm_step_backward_static(ctx, cfg: Config, A_n, theta, lam_n1, lam_n, dtheta, stream=None):
+    """lbm_step_backward with the library's static scratch (no workspace,
+    no allocation)."""
+    n = lbm_state_elems(ctx)
+    npar = lbm_param_elems(ctx)
+    _check(load_library().lbm_step_backward_static(
+        ctx, _ptr(A_n, torch.float32, n, "A_n"),
+        _ptr(theta, torch.float32, npar, "theta", allow_none=cfg.hidden == 0),
+        _ptr(lam_n1, torch.float32, n, "lam_n1"), _ptr(lam_n, torch.float32, n, "lam_n"),
+        _ptr(dtheta, torch.float32, npar, "dtheta", allow_none=cfg.hidden == 0),
+        _stream(stream)), "lbm_step_backward_static")
 
 
 def lbm_step_backward_seq(ctx, cfg: Config, states, theta, lam_a, lam_b, dtheta, ws, stream=None):
