@@ -77,6 +77,8 @@ def parse():
     p.add_argument("--no-si", action="store_true",
                    help="skip the timing of the SI's pipeline (DNS, wide-network training)")
     p.add_argument("--variants", default="bf16,fp16,fp32,bgk,smag")
+    p.add_argument("--settle", type=float, default=2.0,
+                   help="seconds of untimed steps before each D2Q9 leg's warm-up (clock settle)")
     return p.parse_args()
 
 
@@ -90,7 +92,24 @@ def make_state(torch, lbm, inputs, L):
 SMAG_CS = 0.17  # Smagorinsky constant of the comparison collision
 
 
-def time_variant(torch, lbm, inputs, prec, hidden, steps, warmup, A0, collision="bgk"):
+SETTLE_S = 2.0  # untimed running of each leg before its warm-up, so clocks are steady
+
+
+def settle(torch, lbm, L, cfg, A, B, theta, seconds, stream):
+    """Run the leg's own step untimed for `seconds` of wall time (chunks of
+    20 steps): the GPU's clocks ramp over the first few hundred
+    milliseconds of work.  Leaves the state in A."""
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < seconds:
+        lbm.lbm_step(L.ctx, cfg, A, B, theta, 20, stream)
+        torch.cuda.synchronize()
+        steps += 20
+    return steps
+
+
+def time_variant(torch, lbm, inputs, prec, hidden, steps, warmup, A0, collision="bgk",
+                 settle_s=SETTLE_S):
     cfg = lbm.Config(nx=N, ny=N, tau=TAU, hidden=hidden, mlp_prec=prec, out_scale=S_OUT,
                      collision=collision, smag_cs=SMAG_CS if collision == "smagorinsky" else 0.0)
     L = lbm.Lattice(cfg)
@@ -100,6 +119,8 @@ def time_variant(torch, lbm, inputs, prec, hidden, steps, warmup, A0, collision=
     A = A0.clone()
     B = torch.empty_like(A)
     stream = torch.cuda.current_stream()
+    settle_steps = settle(torch, lbm, L, cfg, A, B, theta, settle_s, stream)
+    A.copy_(A0)
     if warmup > 0:
         lbm.lbm_step(L.ctx, cfg, A, B, theta, warmup, stream)
     torch.cuda.synchronize()
@@ -124,6 +145,7 @@ def time_variant(torch, lbm, inputs, prec, hidden, steps, warmup, A0, collision=
     d = diag.cpu().numpy()[0]
     L.close()
     return {"ms_per_step": ms, "mlups": N * N / (ms * 1e-3) / 1e6, "wall_s": wall,
+            "settle_steps": settle_steps,
             "chunk_ms_per_step": {"median": chunk[len(chunk) // 2], "min": chunk[0],
                                   "max": chunk[-1], "chunks": nchunk},
             "mass": float(d[0]), "kinetic_energy": float(d[1]), "nonfinite": int(d[2])}
@@ -224,12 +246,39 @@ def time_d3q19(torch, lbm, inputs, steps):
             torch.cuda.synchronize()
             r["adjoint_ms"] = e0.elapsed_time(e1) / 8
             r["adjoint_mlups"] = n ** 3 / (r["adjoint_ms"] * 1e-3) / 1e6
+        if hidden:
+            r["training_step"] = time_d3q19_training(torch, lbm, inputs, L, cfg, A, ud)
         del A, B
         L.close()
         res[name] = r
         print(f"# d3q19 256^3 {name}: {r['mlups']:.0f} MLUPS" +
               (f", adjoint {r['adjoint_mlups']:.0f} MLUPS" if hidden else ""), file=sys.stderr, flush=True)
     return res
+
+
+def time_d3q19_training(torch, lbm, inputs, L, cfg, A0, ud, reps=5):
+    """One training step of the 3-D workload: 8 forward steps of 256^3 kept as
+    one checkpoint segment, the velocity-MSE loss against a target field, 8
+    adjoint steps through lbm_step_backward_seq, and Adam; median wall time
+    of `reps` steps after two untimed ones."""
+    from paper_2403_18466_amd import training
+    theta = torch.from_numpy(inputs.glorot_params(19, HIDDEN, seed=1)).cuda()
+    ut = (0.9 * ud).contiguous()
+    opt = training.Adam(theta.clone(), lr=1e-4, weight_decay=1e-6)
+    times = []
+    for r in range(reps + 2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss, dth, _ = training.unrolled_loss_and_grad(L, A0, opt.p, ut, 8, 8)
+        opt.step(dth)
+        torch.cuda.synchronize()
+        if r >= 2:
+            times.append(time.perf_counter() - t0)
+    times.sort()
+    ms = 1e3 * times[len(times) // 2]
+    return {"ms": ms, "workload": "D3Q19 256^3 bf16, 8 forward + 8 adjoint steps (one "
+            "checkpoint segment), velocity-MSE loss, Adam", "nonfinite_loss": not bool(
+                torch.isfinite(loss).all())}
 
 
 # multiply-add flops of the 19 -> 300 -> 300 -> 100 -> 19 network per node
@@ -365,31 +414,72 @@ def time_si_pipeline(torch, lbm, inputs):
     return res
 
 
+def host_cpu():
+    """CPU model and the number of CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    return model, ncpu, os.cpu_count() or 1
+
+
 def cpu_baseline():
-    """The FP64 oracle on a bounded sample of the same workload: one step of
-    the same network on a 1024 x 1024 field (serial C, one host thread)."""
+    """The FP64 oracle (serial C) beside the GPU, on the machine's host CPU:
+
+    * value: one host thread, 2 steps of a 4096 x 256 strip of the headline
+      field (same network, tau, initial recipe, periodic in both directions):
+      the per-node work of the headline workload, bounded to about 10 s;
+    * the 64^2 parity workload in full (500 steps, 9->32->32->9);
+    * context: 2 steps of the full 4096^2 headline field with the oracle's
+      row-parallel loops on all host CPUs this process may use."""
     import numpy as np
 
     import oracle
     from paper_2403_18466_amd import inputs
-    n = 1024
-    cfg = oracle.Config(nx=n, ny=n, tau=TAU, hidden=HIDDEN, out_scale=S_OUT)
-    u = inputs.fourier_modes_velocity(n, n, kmax=4, umax=0.05, seed=0)
-    g = oracle.init_equilibrium(cfg, np.ones((1, 1, n, n)), u[None, :, None])
+    model, ncpu, total = host_cpu()
     theta = inputs.glorot_params(9, HIDDEN, seed=1).astype(np.float64)
-    oracle.step(oracle.Config(nx=8, ny=8, tau=TAU, hidden=HIDDEN, out_scale=S_OUT),
-                np.zeros((1, 9, 1, 8, 8)), theta)
+    u = inputs.fourier_modes_velocity(N, N, kmax=4, umax=0.05, seed=0)
+    full = oracle.Config(nx=N, ny=N, tau=TAU, hidden=HIDDEN, out_scale=S_OUT)
+    g = oracle.init_equilibrium(full, np.ones((1, 1, N, N)), u[None, :, None])
+    oracle.set_threads(1)
+    rows = 256
+    strip = oracle.Config(nx=N, ny=rows, tau=TAU, hidden=HIDDEN, out_scale=S_OUT)
+    gs = np.ascontiguousarray(g[:, :, :, :rows])
     t0 = time.perf_counter()
-    steps = 0
-    while True:
-        g = oracle.step(cfg, g, theta)
-        steps += 1
-        if time.perf_counter() - t0 > 10.0 or steps >= 3:
-            break
+    oracle.run(strip, gs, theta, 2)
     dt = time.perf_counter() - t0
-    return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} step(s) of the fp64 oracle on a {n}x{n} field of the same "
-                      f"workload (same network, tau, init recipe), serial C on one host thread",
+    value = N * rows * 2 / dt / 1e6
+    # the 64^2 parity workload in full
+    c1 = oracle.Config(nx=64, ny=64, tau=0.6, hidden=32, out_scale=2.0 ** -4)
+    u1 = inputs.fourier_modes_velocity(64, 64, kmax=4, umax=0.05, seed=0)
+    g1 = oracle.init_equilibrium(c1, np.ones((1, 1, 64, 64)), u1[None, :, None])
+    t1 = time.perf_counter()
+    oracle.run(c1, g1, inputs.glorot_params(9, 32, seed=1).astype(np.float64), 500)
+    d1 = time.perf_counter() - t1
+    # all host threads on the full headline field
+    nt = oracle.set_threads(min(ncpu, 64))
+    t2 = time.perf_counter()
+    oracle.run(full, g, theta, 2)
+    d2 = time.perf_counter() - t2
+    oracle.set_threads(1)
+    return {"value": value, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"2 steps of a {N}x{rows} strip of the headline field (same network, "
+                      f"tau, initial recipe), fp64 oracle, serial C on one host thread "
+                      f"({dt:.1f} s)",
+            "host_cpu": model, "host_cpus_usable": ncpu, "host_cpus_total": total,
+            "parity_workload_64_full": {"steps": 500, "s": d1,
+                                        "mlups": 64 * 64 * 500 / d1 / 1e6, "threads": 1},
+            "headline_4096_two_steps_all_threads": {"threads": nt, "s": d2,
+                                                    "mlups": N * N * 2 / d2 / 1e6},
             "rows": oracle_rows()}
 
 
@@ -458,11 +548,12 @@ def main():
     table = {"bf16": ("bf16", HIDDEN, "bgk"), "fp16": ("fp16", HIDDEN, "bgk"),
              "fp32": ("fp32", HIDDEN, "bgk"), "bgk": ("fp32", 0, "bgk"),
              "smag": ("fp32", 0, "smagorinsky")}
-    for name in ["bf16"] + [v for v in wanted if v != "bf16"]:
+    # the headline leg runs last, after the other legs and its own settle
+    for name in [v for v in wanted if v != "bf16"] + ["bf16"]:
         prec, hidden, coll = table[name]
         steps = args.steps if name != "fp32" else max(1, args.steps // 2)
         variants[name] = time_variant(torch, lbm, inputs, prec, hidden, steps, args.warmup, A0,
-                                      coll)
+                                      coll, args.settle)
         print(f"# {name}: {variants[name]['ms_per_step']:.4f} ms/step, "
               f"{variants[name]['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
 
@@ -506,6 +597,9 @@ def main():
                                "fp32 deviation populations, tau 0.51",
                    "grid": [N, N], "hidden": HIDDEN, "tau": TAU, "out_scale": S_OUT},
         "roofline": roofline,
+        "timing": f"each leg: {args.settle:g} s of untimed steps (clock settle), then --warmup "
+                  "steps from the initial state, then --steps timed with HIP events in up to 5 "
+                  "chunks (chunk spread below); the headline leg runs after the others",
         "variants": {k: {"mlups": v["mlups"], "ms_per_step": v["ms_per_step"],
                          "hbm_frac": BYTES_PER_LUP * N * N / (v["ms_per_step"] * 1e-3) / HBM_PEAK,
                          "chunk_ms_per_step": v["chunk_ms_per_step"],

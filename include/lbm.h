@@ -191,6 +191,20 @@ lbm_status lbm_init(lbm_ctx* ctx, const float* rho, const float* u, float* A0,
 lbm_status lbm_step(lbm_ctx* ctx, float* A, float* B, const float* theta, int32_t nsteps,
                     hipStream_t stream);
 
+/* The float64 reference instance of lbm_step: the same map (collision of
+ * eq. nn-model-full with the kappa projection, force by eq. fext) with the
+ * populations, the parameters and every operation in float64.  A plain
+ * kernel, one thread per node, made to check long float32 / bf16 / fp16 runs
+ * (e.g. thousands of steps of a turbulent field) against the reference
+ * precision on the GPU; it is itself checked against the CPU oracle.
+ * A, B: float64 population arrays ([batch][Q][nz][ny][nx] deviations,
+ * pull-shifted as for lbm_step), ping-pong as lbm_step (result in B for odd
+ * nsteps, in A for even).  theta: packed float64 parameters (may be null when
+ * hidden == 0).  mlp_prec is ignored.  LBM_ERR_UNSUPPORTED for the
+ * Smagorinsky collision and for LBM_NET_LEAKY_300_300_100. */
+lbm_status lbm_step_f64(lbm_ctx* ctx, double* A, double* B, const double* theta, int32_t nsteps,
+                        hipStream_t stream);
+
 /* Moments of the pre-collision state (SI: rho = sum f, rho u = sum f c):
  *   rho = rho0 + sum_q A_q(x - c_q),  u = (j + F/2) / rho,
  * with j = sum_q c_q A_q(x - c_q) and F the body force (the usual

@@ -15,6 +15,7 @@
 #include "kernels_bwd.hpp"
 #include "kernels_diag.hpp"
 #include "kernels_fwd.hpp"
+#include "kernels_ref.hpp"
 #include "lbm.h"
 #include "wide.hpp"
 #include "wide_bwd.hpp"
@@ -515,6 +516,34 @@ lbm_status run_loss(lbm_ctx* ctx, const float* A, const float* ut, double* loss,
   return LBM_OK;
 }
 
+// ---------------------------------------------------- float64 reference
+template <class L, int H>
+lbm_status launch_ref(lbm_ctx* ctx, const double* Ain, double* Aout, const double* theta,
+                      hipStream_t s) {
+  Grid G = grid_of(ctx->cfg);
+  const lbm_config& c = ctx->cfg;
+  RefParams p;
+  p.force_kind = c.force_kind;
+  p.force_k = c.force_k;
+  p.force_amp = c.force_amp;
+  p.rho0 = c.rho0;
+  p.tau = c.tau;
+  p.knn = c.out_scale / c.tau;
+  hipLaunchKernelGGL((ref_step_f64_kernel<L, H>), dim3(blocks_for((long long)G.plane * G.batch, 128)),
+                     dim3(128), 0, s, Ain, Aout, theta, G, p);
+  LBM_LAUNCHED("ref_step_f64_kernel");
+  return LBM_OK;
+}
+
+template <class L>
+lbm_status ref_step(lbm_ctx* ctx, const double* Ain, double* Aout, const double* theta,
+                    hipStream_t s) {
+  switch (ctx->cfg.hidden) {
+    case 0: return launch_ref<L, 0>(ctx, Ain, Aout, theta, s);
+    case 32: return launch_ref<L, 32>(ctx, Ain, Aout, theta, s);
+    default: return launch_ref<L, 64>(ctx, Ain, Aout, theta, s);
+  }
+}
 }  // namespace
 
 #define LBM_GUARD_BEGIN try {
@@ -696,6 +725,31 @@ lbm_status lbm_step(lbm_ctx* ctx, float* A, float* B, const float* theta, int32_
     float* out = buf[(s + 1) & 1];
     st = ctx->cfg.lattice == LBM_D2Q9 ? one_step<D2Q9>(ctx, in, out, theta, stream)
                                       : one_step<D3Q19>(ctx, in, out, theta, stream);
+    if (st != LBM_OK) return st;
+  }
+  return LBM_OK;
+  LBM_GUARD_END
+}
+
+
+lbm_status lbm_step_f64(lbm_ctx* ctx, double* A, double* B, const double* theta, int32_t nsteps,
+                        hipStream_t stream) {
+  LBM_GUARD_BEGIN
+  lbm_status st = check_ctx(ctx);
+  if (st != LBM_OK) return st;
+  const lbm_config& c = ctx->cfg;
+  if (c.collision != LBM_COLLISION_BGK)
+    return fail(LBM_ERR_UNSUPPORTED, "the float64 reference step covers the BGK collision only");
+  if (c.hidden != 0 && c.net != LBM_NET_TANH)
+    return fail(LBM_ERR_UNSUPPORTED, "the float64 reference step covers the tanh networks only");
+  if (!A || !B) return fail(LBM_ERR_INVALID, "null state buffer");
+  if (A == B) return fail(LBM_ERR_INVALID, "A and B must be different buffers");
+  if (nsteps < 1) return fail(LBM_ERR_INVALID, "nsteps must be >= 1");
+  if (c.hidden != 0 && !theta) return fail(LBM_ERR_INVALID, "theta is null");
+  double* buf[2] = {A, B};
+  for (int k = 0; k < nsteps; ++k) {
+    st = c.lattice == LBM_D2Q9 ? ref_step<D2Q9>(ctx, buf[k & 1], buf[(k + 1) & 1], theta, stream)
+                               : ref_step<D3Q19>(ctx, buf[k & 1], buf[(k + 1) & 1], theta, stream);
     if (st != LBM_OK) return st;
   }
   return LBM_OK;

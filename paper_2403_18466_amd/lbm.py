@@ -32,7 +32,7 @@ COLLISIONS = {"bgk": LBM_COLLISION_BGK, "smagorinsky": LBM_COLLISION_SMAGORINSKY
 # Every symbol include/lbm.h declares.
 EXPORTS = (
     "lbm_create", "lbm_destroy", "lbm_state_elems", "lbm_param_elems", "lbm_workspace_bytes",
-    "lbm_lattice_tables", "lbm_init", "lbm_step", "lbm_moments", "lbm_shift",
+    "lbm_lattice_tables", "lbm_init", "lbm_step", "lbm_step_f64", "lbm_moments", "lbm_shift",
     "lbm_step_backward", "lbm_step_backward_static", "lbm_step_backward_seq", "lbm_loss_velocity_mse", "lbm_adam", "lbm_box_filter",
     "lbm_subsample", "lbm_loss_population_sse", "lbm_structure_functions_workspace_bytes",
     "lbm_structure_functions", "lbm_mrt_moment_sums", "lbm_status_str", "lbm_last_error",
@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lbm_lattice_tables": ([i32, ctypes.POINTER(i32), vp, vp], ctypes.c_int),
         "lbm_init": ([vp, vp, vp, vp, vp], ctypes.c_int),
         "lbm_step": ([vp, vp, vp, vp, i32, vp], ctypes.c_int),
+        "lbm_step_f64": ([vp, vp, vp, vp, i32, vp], ctypes.c_int),
         "lbm_moments": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "lbm_shift": ([vp, vp, vp, i32, vp], ctypes.c_int),
         "lbm_step_backward": ([vp, vp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
@@ -228,6 +229,17 @@ def lbm_step(ctx, cfg: Config, A, B, theta, nsteps: int, stream=None):
     _check(load_library().lbm_step(ctx, _ptr(A, torch.float32, n, "A"),
                                    _ptr(B, torch.float32, n, "B"), th, int(nsteps),
                                    _stream(stream)), "lbm_step")
+    return B if nsteps % 2 == 1 else A
+
+
+def lbm_step_f64(ctx, cfg: Config, A, B, theta, nsteps: int, stream=None):
+    """The float64 reference step (A, B, theta float64 device tensors);
+    returns the buffer that holds the result, as lbm_step."""
+    n = lbm_state_elems(ctx)
+    th = _ptr(theta, torch.float64, lbm_param_elems(ctx), "theta", allow_none=cfg.hidden == 0)
+    _check(load_library().lbm_step_f64(ctx, _ptr(A, torch.float64, n, "A"),
+                                       _ptr(B, torch.float64, n, "B"), th, int(nsteps),
+                                       _stream(stream)), "lbm_step_f64")
     return B if nsteps % 2 == 1 else A
 
 

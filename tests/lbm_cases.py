@@ -142,3 +142,23 @@ def plain_rounding_config(ocfg, prec):
 def exact_config(ocfg):
     import dataclasses
     return dataclasses.replace(ocfg, quant="none", quant_weights=True)
+
+
+def spectrum(u):
+    """Shell-summed 1/2 |u_hat(k)|^2 of a (2, n, n) velocity field, float64."""
+    n = u.shape[-1]
+    uh = np.fft.fft2(u, axes=(-2, -1)) / (n * n)
+    e = 0.5 * (np.abs(uh) ** 2).sum(0)
+    k = np.fft.fftfreq(n, d=1.0 / n)
+    kk = np.sqrt(k[:, None] ** 2 + k[None, :] ** 2)
+    shell = np.rint(kk).astype(int)
+    return np.bincount(shell.ravel(), weights=e.ravel())[: n // 2]
+
+
+def spectral_errors(E, E_ref):
+    """Energy-weighted relative error over k >= 1 and the largest relative
+    error over the shells that hold at least 0.1% of the energy."""
+    k = np.arange(1, len(E_ref))
+    w = E_ref[k]
+    sig = w > 1e-3 * w.sum()
+    return float(np.abs(E[k] - w).sum() / w.sum()), float(np.abs(E[k][sig] / w[sig] - 1).max())
