@@ -590,15 +590,33 @@ struct CoopLayout {
   // fragments of one group, in slot order
   static constexpr int FDY = 0, FH2 = FDY + S::QB, FD2 = FH2 + S::HB, FH1 = FD2 + S::HB,
                        FD1 = FH1 + S::HB, FX0 = FD1 + S::HB, NFR = FX0 + S::KX;
-  static constexpr int XS = 16 * S::KX + 4;                             // x0 row (16-bit elements)
-  static constexpr int SD = 16 * (S::QB > S::KX ? S::QB : S::KX) + 4;  // dy / dx row (floats)
   // weight fragments: transposed for the backward products, then W1 and W2
   static constexpr int NFB = S::HB * S::QB + S::HB * S::HB + S::KX * S::HB;
   static constexpr int NFF = S::HB * S::KX + S::HB * S::HB;
-  static constexpr int x_bytes = 64 * XS * 2, d_bytes = 64 * SD * 4, slot_bytes = NFR * 512;
-  static constexpr int wave_bytes = x_bytes + d_bytes + slot_bytes;
-  static constexpr int bytes = (NFB + NFF) * 512 + H * 4 + NW * wave_bytes;
-  static constexpr bool ok = P != P_F32 && bytes <= 160 * 1024 && S::n * 4 <= NW * wave_bytes;
+  static constexpr int wts_bytes = (NFB + NFF) * 512 + H * 4;
+  static constexpr int slot_bytes = NFR * 512;
+  // Per-wavefront staging, one of two layouts.
+  // Item layout: the 64 nodes' x0 rows (16-bit) and dy rows (float32,
+  // overwritten by dx group by group), padded to whole 16-wide chunks.
+  static constexpr int XS = 16 * S::KX + 4;                             // x0 row (16-bit elements)
+  static constexpr int SD = 16 * (S::QB > S::KX ? S::QB : S::KX) + 4;  // dy / dx row (floats)
+  static constexpr int item_wave_bytes = 64 * XS * 2 + 64 * SD * 4 + slot_bytes;
+  // Compact layout, where the item layout does not fit (D3Q19): x0 and dy
+  // as 16-bit rows of exactly the features in use (Q + 1 and Q, rounded up
+  // to 4; the operand reads past them are zeros), dx as float32 rows of one
+  // 16-node group.
+  static constexpr int NXF = (S::Q + 1 + 3) / 4 * 4, NQF = (S::Q + 3) / 4 * 4;
+  static constexpr int compact_wave_bytes = 64 * NXF * 2 + 64 * NQF * 2 + 16 * NXF * 4 + slot_bytes;
+  static constexpr bool COMPACT = wts_bytes + NW * item_wave_bytes > 160 * 1024;
+  static constexpr int wave_bytes = COMPACT ? compact_wave_bytes : item_wave_bytes;
+  // byte offsets within a wavefront's region: x0 rows, dy rows, dx rows, slot
+  static constexpr int xoff = 0;
+  static constexpr int doff = COMPACT ? 64 * NXF * 2 : 64 * XS * 2;
+  static constexpr int dxoff = COMPACT ? doff + 64 * NQF * 2 : doff;
+  static constexpr int soff = COMPACT ? dxoff + 16 * NXF * 4 : doff + 64 * SD * 4;
+  static constexpr int bytes = wts_bytes + NW * wave_bytes;
+  static constexpr bool ok = P != P_F32 && bytes <= 160 * 1024 && S::n * 4 <= NW * wave_bytes &&
+                             wave_bytes % 16 == 0;
   // tile t: kind 2 = dW2, 4 = b2, 1 = dW1|b1, 3 = dW3, 5 = b3; its row and
   // column block; the slot fragments of its A and B operands (-1: ones)
   static constexpr int kind(int t) {
@@ -804,10 +822,14 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   const Fr* W2F = W1F + S::HB * S::KX * 64;
 
   unsigned char* mine = wl + wave * CL::wave_bytes;
-  unsigned short* X = reinterpret_cast<unsigned short*>(mine);  // [64][XS] x0, operand format
-  float* D = reinterpret_cast<float*>(mine + CL::x_bytes);      // [64][SD] dy, then dx
-  unsigned char* slot = mine + CL::x_bytes + CL::d_bytes;
-  const unsigned char* slots = wl + CL::x_bytes + CL::d_bytes;  // slot w at w * wave_bytes
+  // item layout: X [64][XS] x0 (operand format), D [64][SD] dy then dx (float32);
+  // compact layout: X [64][NXF] x0, Y [64][NQF] dy (operand format), DX [16][NXF] dx
+  unsigned short* X = reinterpret_cast<unsigned short*>(mine + CL::xoff);
+  float* D = reinterpret_cast<float*>(mine + CL::doff);
+  unsigned short* Y = reinterpret_cast<unsigned short*>(mine + CL::doff);
+  float* DX = reinterpret_cast<float*>(mine + CL::dxoff);
+  unsigned char* slot = mine + CL::soff;
+  const unsigned char* slots = wl + CL::soff;  // slot w at w * wave_bytes
 
   // contraction-layout addresses: this lane's read offset, and the write
   // offsets of its four D-layout values (feature 4 lg + r, node li)
@@ -865,25 +887,48 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
     collide_adjoint<L>(gc, mc, rho0, omega, F3, Fc.kind != 0, nu, lam);
 
     // stage x0 (rounded to the operand format) and dy = k nu, node-major rows
+    if constexpr (CL::COMPACT) {
 #pragma unroll
-    for (int c = 0; c < 4 * S::KX; ++c) {
-      f4 v;
+      for (int c = 0; c < CL::NXF / 4; ++c) {
+        f4 v;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int kk = 4 * c + r;
-        v[r] = kk < Q ? gc[kk] : (kk == Q ? 1.f : 0.f);
+        for (int r = 0; r < 4; ++r) {
+          int kk = 4 * c + r;
+          v[r] = kk < Q ? gc[kk] : (kk == Q ? 1.f : 0.f);
+        }
+        *reinterpret_cast<Fr*>(X + lane * CL::NXF + 4 * c) = to_frag<P>(v);
       }
-      *reinterpret_cast<Fr*>(X + lane * CL::XS + 4 * c) = to_frag<P>(v);
-    }
 #pragma unroll
-    for (int c = 0; c < 4 * S::QB; ++c) {
-      f4 v;
+      for (int c = 0; c < CL::NQF / 4; ++c) {
+        f4 v;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int q = 4 * c + r;
-        v[r] = q < Q ? knn * nu[q] : 0.f;
+        for (int r = 0; r < 4; ++r) {
+          int q = 4 * c + r;
+          v[r] = q < Q ? knn * nu[q] : 0.f;
+        }
+        *reinterpret_cast<Fr*>(Y + lane * CL::NQF + 4 * c) = to_frag<P>(v);
       }
-      *reinterpret_cast<f4*>(D + lane * CL::SD + 4 * c) = v;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4 * S::KX; ++c) {
+        f4 v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int kk = 4 * c + r;
+          v[r] = kk < Q ? gc[kk] : (kk == Q ? 1.f : 0.f);
+        }
+        *reinterpret_cast<Fr*>(X + lane * CL::XS + 4 * c) = to_frag<P>(v);
+      }
+#pragma unroll
+      for (int c = 0; c < 4 * S::QB; ++c) {
+        f4 v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int q = 4 * c + r;
+          v[r] = q < Q ? knn * nu[q] : 0.f;
+        }
+        *reinterpret_cast<f4*>(D + lane * CL::SD + 4 * c) = v;
+      }
     }
     wave_lds_sync();
     // the next item's loads are in flight while this item's network runs
@@ -909,8 +954,16 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll
         for (int i = 0; i < S::HB * S::KX; ++i) w1[i] = W1F[64 * i + lane];
 #pragma unroll
-        for (int c = 0; c < S::KX; ++c)
-          xin[c] = *reinterpret_cast<const Fr*>(X + nrow * CL::XS + 16 * c + 4 * lg);
+        for (int c = 0; c < S::KX; ++c) {
+          if constexpr (CL::COMPACT) {
+            // features past NXF are zeros and are not stored
+            xin[c] = 16 * c + 4 * lg < CL::NXF
+                         ? *reinterpret_cast<const Fr*>(X + nrow * CL::NXF + 16 * c + 4 * lg)
+                         : Fr{};
+          } else {
+            xin[c] = *reinterpret_cast<const Fr*>(X + nrow * CL::XS + 16 * c + 4 * lg);
+          }
+        }
         f4 a1[S::HB];
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob)
@@ -949,7 +1002,13 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
         for (int i = 0; i < S::HB * S::QB; ++i) w3t[i] = W3T[64 * i + lane];
 #pragma unroll
         for (int qc = 0; qc < S::QB; ++qc) {
-          dyf[qc] = to_frag<P>(*reinterpret_cast<const f4*>(D + nrow * CL::SD + 16 * qc + 4 * lg));
+          if constexpr (CL::COMPACT) {
+            dyf[qc] = 16 * qc + 4 * lg < CL::NQF
+                          ? *reinterpret_cast<const Fr*>(Y + nrow * CL::NQF + 16 * qc + 4 * lg)
+                          : Fr{};
+          } else {
+            dyf[qc] = to_frag<P>(*reinterpret_cast<const f4*>(D + nrow * CL::SD + 16 * qc + 4 * lg));
+          }
           put_t(CL::FDY + qc, dyf[qc]);
         }
         // d2 = (W3^T dy) (1 - t2^2),  d1 = (W2^T d2) (1 - t1^2)
@@ -980,13 +1039,27 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
           d1f[ob] = to_frag<P>(a3[ob] * (1.f / sc) * (1.f - t1[ob] * t1[ob]));
           put_t(CL::FD1 + ob, d1f[ob]);
         }
-        // dx = W1^T d1 over this group's rows, whose dy has been read
+        // dx = W1^T d1 over this group's rows, whose dy has been read (item
+        // layout), or into the group's dx rows (compact layout); the owner
+        // lanes of the group's nodes add it to their lam
         wave_lds_sync();
 #pragma unroll
         for (int c = 0; c < S::KX; ++c) {
           f4 a = mma_row<P, S::HB>(f4{0.f, 0.f, 0.f, 0.f}, w1t + c * S::HB, d1f);
           a = a * (1.f / sc);
-          *reinterpret_cast<f4*>(D + nrow * CL::SD + 16 * c + 4 * lg) = a;
+          if constexpr (CL::COMPACT) {
+            if (16 * c + 4 * lg < CL::NXF)
+              *reinterpret_cast<f4*>(DX + li * CL::NXF + 16 * c + 4 * lg) = a;
+          } else {
+            *reinterpret_cast<f4*>(D + nrow * CL::SD + 16 * c + 4 * lg) = a;
+          }
+        }
+        if constexpr (CL::COMPACT) {
+          wave_lds_sync();
+          if ((lane >> 4) == jg) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) lam[q] += DX[li * CL::NXF + q];
+          }
         }
       }
       __syncthreads();
@@ -994,8 +1067,10 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
       coop_tiles_of<CL, P>(wave, acc, slots, rdo);
     }
     wave_lds_sync();
+    if constexpr (!CL::COMPACT) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) lam[q] += D[lane * CL::SD + q];
+      for (int q = 0; q < Q; ++q) lam[q] += D[lane * CL::SD + q];
+    }
     if (act) scatter_item<L>(rL0, G, t, lam);
     wave_lds_sync();
   }

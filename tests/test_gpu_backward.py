@@ -133,8 +133,8 @@ def test_nlbm_adjoint_reduced_precision(lbm, prec):
     ("D2Q9", "fp16", 64, (1, 40, 300), 3, 1),   # 600 items of up to 64 nodes
     ("D2Q9", "bf16", 32, (1, 64, 200), 2, 0),
     ("D2Q9", "fp16", 32, (1, 33, 70), 2, 1),    # fewer items than workgroups
-    ("D3Q19", "bf16", 32, (9, 10, 70), 2, 2),   # 360 items, three-component force, per-wave kernel
-    ("D3Q19", "fp16", 64, (6, 7, 20), 1, 0),    # the per-wave kernel at 16 bits
+    ("D3Q19", "bf16", 32, (9, 10, 70), 2, 2),   # 360 items, three-component force, compact staging
+    ("D3Q19", "fp16", 64, (6, 7, 20), 1, 0),    # the cooperative kernel, compact staging
 ])
 def test_nlbm_adjoint_16bit_per_block(lbm, lat, prec, H, shape, batch, force):
     """16-bit adjoint on grids large enough that every workgroup runs several
@@ -317,7 +317,7 @@ def test_unrolled_gradient_d3q19(lbm, prec):
     ("D2Q9", "bf16", 64, (1, 48, 70), 3),   # cooperative kernel, odd count
     ("D2Q9", "fp16", 32, (1, 33, 64), 4),   # cooperative kernel, even count
     ("D2Q9", "fp32", 64, (1, 20, 40), 2),   # per-wave kernel
-    ("D3Q19", "bf16", 64, (6, 7, 20), 3),   # per-wave kernel, 16-bit
+    ("D3Q19", "bf16", 64, (6, 7, 20), 3),   # cooperative kernel, compact staging
     ("D2Q9", "bgk", 0, (1, 16, 16), 3),     # no parameters: steps one by one
     ("D2Q9", "bf16", 64, (1, 16, 70), 1),   # a single step
 ])

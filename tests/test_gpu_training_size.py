@@ -256,14 +256,16 @@ def test_d3q19_256_unrolled_8_steps_sampled(cfg5_case, prec):
         f"fp64 {fmt_blocks(block_errors(pdth, xdth, BLOCKS19))}")
     log(msg + f"; dtheta vs kernel scheme {e_k:.2e}; |gpu-fp64| / |plain-fp64| {r_th:.2f}")
     # The kernel rounds its backward operands (dy, d2, d1) to the format
-    # before each product; the emulation passes rounding straight through.
-    # With the loss on a handful of nodes the bias gradients are sums with
-    # heavy cancellation (float32 already shows 5x the weight blocks' relative
-    # error on b1, b2), which amplifies that per-node rounding: measured 0.14
-    # (b1) and 0.075 (b2) of the block against 0.003 for the plain-rounding
-    # scheme; the weight blocks 0.010-0.015, dL/dA0 3.3e-4.
+    # before each product, and forms the bias gradients from those operands
+    # (b1 through its constant input column, b2 and b3 as products with a
+    # ones fragment); the emulation passes rounding straight through.  With
+    # the loss on a handful of nodes the bias gradients are sums with heavy
+    # cancellation (float32 already shows 5x the weight blocks' relative error
+    # on them), which amplifies that per-node 2^-9 rounding: measured 0.14
+    # (b1), 0.14 (b2) and 0.079 (b3) of the block, against 0.003 for the
+    # plain-rounding scheme; the weight blocks 0.010-0.015, dL/dA0 3.3e-4.
     assert abs(gl / xl - 1) < 1e-3 and e_lam < 1e-3
+    bias = (BLOCKS19[1], BLOCKS19[3], BLOCKS19[5])
     for (a, b), (_, err) in zip(zip(BLOCKS19[:-1], BLOCKS19[1:]),
                                 block_errors(gdth, kdth, BLOCKS19)):
-        bar = 0.25 if a in (BLOCKS19[1], BLOCKS19[3]) else 0.03
-        assert err < bar
+        assert err < (0.25 if a in bias else 0.03)
