@@ -333,8 +333,16 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
   stage_issue(stage0, WL::step_offset(0), WL::step_bytes(0));
   __syncthreads();
 
+  // the walk state is wave-uniform: keep it in scalar registers
+  auto uniform = [](ItemWalk& w) {
+    w.xc = __builtin_amdgcn_readfirstlane(w.xc);
+    w.y = __builtin_amdgcn_readfirstlane(w.y);
+    w.z = __builtin_amdgcn_readfirstlane(w.z);
+    w.b = __builtin_amdgcn_readfirstlane(w.b);
+  };
   ItemWalk cur, nxt;
   cur.start(it0 < nitems ? it0 : nitems - 1, nxc, G);
+  uniform(cur);
   float gn[Q];
   if (it0 < nitems) {
     const Item t0 = cur.item(G, lane);
@@ -353,6 +361,7 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
     wave_lds_sync();
     nxt = cur;
     nxt.next(nxc, G);
+    uniform(nxt);
 
     static_for<NS>([&](auto swc) {
       constexpr int sw = decltype(swc)::value;
@@ -364,7 +373,7 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
         constexpr int s = decltype(sc)::value;
         constexpr int sn = (s + 1) % WL::NSTEP;
         stage_issue(s % 2 == 0 ? stage1 : stage0, WL::step_offset(sn), WL::step_bytes(sn));
-        if constexpr (s == 1 && sw == NS - 1) {
+        if constexpr (s == WL::NSTEP - 1 && sw == NS - 1) {
           if (more) {
             const Item tn = nxt.item(G, lane);
             gather_rows<L>(src, row_offsets(G, Q, tn.b, tn.y, tn.z), tn, gn);
