@@ -151,6 +151,40 @@ def time_variant(torch, lbm, inputs, prec, hidden, steps, warmup, A0, collision=
             "mass": float(d[0]), "kinetic_energy": float(d[1]), "nonfinite": int(d[2])}
 
 
+def time_kolmogorov(torch, lbm, inputs, steps):
+    """The Kolmogorov workload's step: D2Q9 1024^2, F_x = 1e-5 sin(2 pi 4 y /
+    1024) through the exact difference method, tau 0.51, 9->64->64->9 tanh
+    (s_out 2^-6), bf16 and fp32 networks.  Its two state arrays (75 MB) stay
+    in the 256 MB last-level cache, so this is not an HBM-roofline figure."""
+    n = 1024
+    u = inputs.fourier_modes_velocity(n, n, kmax=4, umax=0.01, seed=0).astype("float32")
+    ud = torch.from_numpy(u).reshape(1, 2, 1, n, n).cuda()
+    res = {}
+    for prec in ("bf16", "fp32"):
+        cfg = lbm.Config(nx=n, ny=n, tau=TAU, hidden=HIDDEN, mlp_prec=prec, out_scale=S_OUT,
+                         force_kind=lbm.LBM_FORCE_KOLMOGOROV, force_k=4, force_amp=1e-5)
+        L = lbm.Lattice(cfg)
+        A = L.init(torch.ones((1, 1, n, n), device="cuda"), ud)
+        B = torch.empty_like(A)
+        theta = torch.from_numpy(inputs.glorot_params(9, HIDDEN, seed=1)).cuda()
+        lbm.lbm_step(L.ctx, cfg, A, B, theta, 200)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lbm.lbm_step(L.ctx, cfg, A, B, theta, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[prec] = {"ms_per_step": ms, "mlups": n * n / (ms * 1e-3) / 1e6}
+        L.close()
+    res["workload"] = ("D2Q9 1024^2 Kolmogorov forcing A 1e-5, k 4 (EDM), tau 0.51, 9-64-64-9 "
+                       "tanh; cache-resident")
+    print(f"# kolmogorov 1024^2: bf16 {res['bf16']['mlups']:.0f} MLUPS, fp32 "
+          f"{res['fp32']['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    return res
+
+
 def time_training(torch, lbm, inputs, prec, reps):
     """One training step of the unrolled-training workload: 8 fields of
     256 x 256, 32 unrolled steps with a checkpoint every 8 (forward, segment
@@ -620,6 +654,7 @@ def main():
             "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": BYTES_PER_LUP * N * N / (smag["ms_per_step"] * 1e-3) / HBM_PEAK,
             "collision": f"Smagorinsky LES, C_s = {SMAG_CS}, tau 0.51, same field"}
+    result["kolmogorov_1024"] = time_kolmogorov(torch, lbm, inputs, max(100, args.steps))
     if not args.no_d3q19:
         result["d3q19_256"] = time_d3q19(torch, lbm, inputs, max(10, args.steps // 5))
     if not args.no_wide:

@@ -233,7 +233,10 @@ lbm_status lbm_shift(lbm_ctx* ctx, const float* src, float* dst, int32_t directi
  * The step is recomputed from A_n inside the kernel (no activations are
  * stored).  In the bf16/fp16 modes the rounding of the forward operands is
  * passed straight through and the backward contractions use the same operand
- * precision.  ws: device workspace of at least lbm_workspace_bytes() bytes
+ * precision.  fp16 operands cover 6e-8 .. 65504 only: where the network's
+ * part of the adjoint, (s_out / tau) times lam^{n+1} projected, falls below
+ * that (a mean loss over many nodes), it flushes to zero; scale lam^{n+1}
+ * by a power of two (loss scaling) or use bf16, whose range is float32's.  ws: device workspace of at least lbm_workspace_bytes() bytes
  * for the per-workgroup partial parameter gradients, which are summed in a
  * fixed order (the result is bit-reproducible).  dtheta may be null only
  * when hidden == 0.  lam_n must not alias lam_n1 or A_n.

@@ -47,29 +47,26 @@ struct Grid {
   int plane;  // nx * ny * nz
 };
 
-// Body force of eq. fext at integer node (x, y, z).
+// Body force of eq. fext at integer node (x, y, z), read from tables that
+// the context fills once in float64 on the host (rounded to float32):
+// F_x(y) for both forcing kinds, F_y(z) and F_z(x) for the three-component
+// forcing.  The pointers are null where a kind does not use them.
 struct Force {
-  int kind;  // 0 none, 1 Kolmogorov F_x(y), 2 three-component sine
-  int k;
-  float amp;
+  int kind;           // 0 none, 1 Kolmogorov F_x(y), 2 three-component sine
+  const float* fx_y;  // [ny]
+  const float* fy_z;  // [nz]
+  const float* fz_x;  // [nx]
 };
 
-__device__ inline float sin_frac(long long num, long long den) {
-  // sin(2 pi num / den) with the argument reduced exactly in integers
-  long long r = num % den;
-  if (r < 0) r += den;
-  return (float)sinpi(2.0 * (double)r / (double)den);
-}
-
+// Lanes past the end of a row (x >= nx, whose results are never stored)
+// read the table entry of the row's last node.
 __device__ inline void body_force(const Force& f, const Grid& G, int x, int y, int z,
                                   float F[3]) {
   F[0] = F[1] = F[2] = 0.f;
-  if (f.kind == 1) {
-    F[0] = f.amp * sin_frac((long long)f.k * y, G.ny);
-  } else if (f.kind == 2) {
-    F[0] = f.amp * sin_frac((long long)f.k * y, G.ny);
-    F[1] = f.amp * sin_frac((long long)f.k * z, G.nz);
-    F[2] = f.amp * sin_frac((long long)f.k * x, G.nx);
+  if (f.kind != 0) F[0] = f.fx_y[y];
+  if (f.kind == 2) {
+    F[1] = f.fy_z[z];
+    F[2] = f.fz_x[x < G.nx ? x : G.nx - 1];
   }
 }
 

@@ -48,6 +48,8 @@ struct lbm_ctx {
   unsigned char* wide_bpacked;
   // partial sums of the moment-space analysis (D3Q19 contexts)
   double* mrt;
+  // body force tables F_x(y), F_y(z), F_z(x) (float32, from float64 on the host)
+  float* force_tab;
 };
 
 namespace {
@@ -87,12 +89,25 @@ Grid grid_of(const lbm_config& c) {
   return G;
 }
 
-Force force_of(const lbm_config& c) {
+Force force_of(const lbm_ctx* ctx) {
+  const lbm_config& c = ctx->cfg;
   Force f;
   f.kind = c.force_kind;
-  f.k = c.force_k;
-  f.amp = (float)c.force_amp;
+  f.fx_y = ctx->force_tab;
+  f.fy_z = ctx->force_tab ? ctx->force_tab + c.ny : nullptr;
+  f.fz_x = ctx->force_tab ? ctx->force_tab + c.ny + c.nz : nullptr;
   return f;
+}
+
+// amp sin(2 pi k s / n) for s = 0 .. n - 1, the argument reduced exactly in
+// integers, in float64, rounded once to float32.
+void force_table(double amp, int k, int n, float* out) {
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int s = 0; s < n; ++s) {
+    long long r = ((long long)k * s) % n;
+    if (r < 0) r += n;
+    out[s] = (float)(amp * std::sin(two_pi * (double)r / (double)n));
+  }
 }
 
 size_t param_count(int lat, int H, int net) {
@@ -307,7 +322,7 @@ lbm_status run_moments(lbm_ctx* ctx, const float* A, float* rho, float* u, doubl
   Grid G = grid_of(ctx->cfg);
   const int nxc = (G.nx + 255) / 256;
   hipLaunchKernelGGL(moments_kernel<L>, dim3(MOMENT_BLOCKS, G.batch), dim3(256), 0, s, A, rho, u,
-                     ctx->partial, G, (float)ctx->cfg.rho0, force_of(ctx->cfg), nxc);
+                     ctx->partial, G, (float)ctx->cfg.rho0, force_of(ctx), nxc);
   LBM_LAUNCHED("moments_kernel");
   if (diag) {
     hipLaunchKernelGGL(diag_reduce_kernel, dim3(G.batch), dim3(256), 0, s, ctx->partial, diag,
@@ -324,7 +339,7 @@ lbm_status launch_bgk_v(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t
   int nxc = (G.nx + 255) / 256;
   long long nblk = (long long)nxc * ((G.ny + R - 1) / R) * G.nz * G.batch;
   hipLaunchKernelGGL((bgk_step_kernel<L, R, NT, SMAG>), dim3((unsigned)nblk), dim3(256), 0, s,
-                     Ain, Aout, G, force_of(c), (float)c.rho0, (float)(1.0 / c.tau), nxc,
+                     Ain, Aout, G, force_of(ctx), (float)c.rho0, (float)(1.0 / c.tau), nxc,
                      (float)c.tau, (float)(1.5 / c.tau), (float)(3.0 * c.smag_cs * c.smag_cs));
   LBM_LAUNCHED("bgk_step_kernel");
   return LBM_OK;
@@ -371,7 +386,7 @@ lbm_status launch_nlbm(lbm_ctx* ctx, const float* Ain, float* Aout, const float*
   unsigned blocks = 0;
   lbm_status st = persistent_blocks(ctx, kernel, 64 * wb, wb, nitems, blocks);
   if (st != LBM_OK) return st;
-  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(64 * wb), 0, s, Ain, Aout, theta, G, force_of(c),
+  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(64 * wb), 0, s, Ain, Aout, theta, G, force_of(ctx),
                      (float)c.rho0, (float)(1.0 / c.tau), (float)(c.out_scale / c.tau),
                      (int)nitems, nxc);
   LBM_LAUNCHED("nlbm_step_kernel");
@@ -417,7 +432,7 @@ lbm_status launch_wide(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t 
   const long long per = (nitems + nb * C::WAVES - 1) / (nb * C::WAVES);
   const lbm_config& c = ctx->cfg;
   hipError_t e = wide_step_launch(L::Q == 19, P, (unsigned)nb, s, Ain, Aout, ctx->wide_packed, G,
-                                  force_of(c), (float)c.rho0, (float)(1.0 / c.tau),
+                                  force_of(ctx), (float)c.rho0, (float)(1.0 / c.tau),
                                   (float)(c.out_scale / c.tau), (int)per, (int)nitems, nxc);
   if (e != hipSuccess)
     return fail(LBM_ERR_HIP, std::string("launch of wide_step_kernel: ") + hipGetErrorString(e));
@@ -457,7 +472,7 @@ lbm_status launch_bwd(lbm_ctx* ctx, const float* A, const float* theta, const fl
   float* part = static_cast<float*>(ws);
   const unsigned blocks = bwd_blocks(ctx->ncu);
   hipError_t e = nlbm_bwd_launch(L::Q == 19, H, P, blocks, s, A, theta, lam1, lam0, part, G,
-                                 force_of(c), (float)c.rho0, (float)(1.0 / c.tau),
+                                 force_of(ctx), (float)c.rho0, (float)(1.0 / c.tau),
                                  (float)(c.out_scale / c.tau), (int)nitems, nxc, accum);
   if (e != hipSuccess)
     return fail(LBM_ERR_HIP, std::string("launch of nlbm_backward_kernel: ") + hipGetErrorString(e));
@@ -492,7 +507,7 @@ lbm_status run_backward(lbm_ctx* ctx, const float* A, const float* theta, const 
     int nxc = (G.nx + 255) / 256;
     long long nblk = (long long)nxc * G.ny * G.nz * G.batch;
     hipLaunchKernelGGL(bgk_backward_kernel<L>, dim3((unsigned)nblk), dim3(256), 0, s, A, lam1,
-                       lam0, G, force_of(c), (float)c.rho0, (float)(1.0 / c.tau), nxc);
+                       lam0, G, force_of(ctx), (float)c.rho0, (float)(1.0 / c.tau), nxc);
     LBM_LAUNCHED("bgk_backward_kernel");
     return LBM_OK;
   }
@@ -508,7 +523,7 @@ lbm_status run_loss(lbm_ctx* ctx, const float* A, const float* ut, double* loss,
   const int nblk = MOM_BLOCKS;
   double count = (double)G.plane * G.batch * L::D;
   hipLaunchKernelGGL(loss_kernel<L>, dim3(nblk), dim3(256), 0, s, A, ut, dLdA, ctx->partial, G,
-                     (float)ctx->cfg.rho0, force_of(ctx->cfg), 1.0 / count);
+                     (float)ctx->cfg.rho0, force_of(ctx), 1.0 / count);
   LBM_LAUNCHED("loss_kernel");
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, ctx->partial, nblk,
                      1.0 / count, loss);
@@ -584,6 +599,7 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
   ctx->wide_bidx = nullptr;
   ctx->wide_bpacked = nullptr;
   ctx->mrt = nullptr;
+  ctx->force_tab = nullptr;
   size_t bytes = sizeof(double) * 3 * (size_t)(MOM_BLOCKS > MOMENT_BLOCKS ? MOM_BLOCKS : MOMENT_BLOCKS) *
                  (size_t)cfg->batch;
   hipError_t e = hipMalloc(&ctx->partial, bytes);
@@ -591,6 +607,21 @@ lbm_status lbm_create(const lbm_config* cfg, lbm_ctx** out) {
     delete ctx;
     return fail(LBM_ERR_HIP, std::string("hipMalloc of the reduction buffer: ") +
                                  hipGetErrorString(e));
+  }
+  if (cfg->force_kind != LBM_FORCE_NONE) {
+    std::vector<float> tab((size_t)cfg->ny + cfg->nz + cfg->nx, 0.f);
+    force_table(cfg->force_amp, cfg->force_k, cfg->ny, tab.data());
+    if (cfg->force_kind == LBM_FORCE_SINE3) {
+      force_table(cfg->force_amp, cfg->force_k, cfg->nz, tab.data() + cfg->ny);
+      force_table(cfg->force_amp, cfg->force_k, cfg->nx, tab.data() + cfg->ny + cfg->nz);
+    }
+    e = hipMalloc(&ctx->force_tab, sizeof(float) * tab.size());
+    if (e == hipSuccess)
+      e = hipMemcpy(ctx->force_tab, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      lbm_destroy(ctx);
+      return fail(LBM_ERR_HIP, std::string("the body-force table: ") + hipGetErrorString(e));
+    }
   }
   if (cfg->lattice == LBM_D3Q19) {
     e = hipMalloc(&ctx->mrt, sizeof(double) * 19 * DIAG_BLOCKS * 5);
@@ -642,6 +673,7 @@ lbm_status lbm_destroy(lbm_ctx* ctx) {
   if (ctx->wide_bidx) (void)hipFree(ctx->wide_bidx);
   if (ctx->wide_bpacked) (void)hipFree(ctx->wide_bpacked);
   if (ctx->mrt) (void)hipFree(ctx->mrt);
+  if (ctx->force_tab) (void)hipFree(ctx->force_tab);
   delete ctx;
   return LBM_OK;
   LBM_GUARD_END
@@ -801,7 +833,7 @@ lbm_status lbm_step_backward(lbm_ctx* ctx, const float* A_n, const float* theta,
     const lbm_config& c = ctx->cfg;
     hipError_t e = wide_bwd_launch(c.lattice == LBM_D3Q19, prec_of(c.mlp_prec), stream, A_n, theta,
                                    lam_n1, lam_n, dtheta, ws, ctx->wide_bidx, ctx->wide_bpacked,
-                                   grid_of(c), force_of(c), (float)c.rho0, (float)(1.0 / c.tau),
+                                   grid_of(c), force_of(ctx), (float)c.rho0, (float)(1.0 / c.tau),
                                    (float)(c.out_scale / c.tau));
     if (e != hipSuccess)
       return fail(LBM_ERR_HIP, std::string("wide-network adjoint: ") + hipGetErrorString(e));
@@ -1033,7 +1065,7 @@ lbm_status lbm_mrt_moment_sums(lbm_ctx* ctx, const float* A_n, const float* A_n1
     return fail(LBM_ERR_UNSUPPORTED, "the moment matrix M is given for D3Q19 only");
   Grid G = grid_of(ctx->cfg);
   hipLaunchKernelGGL(mrt_sums_kernel, dim3(DIAG_BLOCKS, 19), dim3(256), 0, stream, A_n, A_n1, G,
-                     force_of(ctx->cfg), (float)ctx->cfg.rho0, ctx->mrt);
+                     force_of(ctx), (float)ctx->cfg.rho0, ctx->mrt);
   LBM_LAUNCHED("mrt_sums_kernel");
   hipLaunchKernelGGL(mrt_reduce_kernel, dim3(1), dim3(128), 0, stream, ctx->mrt, DIAG_BLOCKS, stats);
   LBM_LAUNCHED("mrt_reduce_kernel");

@@ -191,27 +191,6 @@ __device__ __forceinline__ void lds_pipeline(Rd&& rd, Pre&& pre, Cs&& cs) {
   });
 }
 
-// Body force at integer node (x, y, z) in float32: the argument 2 pi k y / n
-// is reduced exactly in integers, then sin(pi t) with t in [0, 2) (error a
-// few 1e-7 of the amplitude).
-__device__ inline float sin_frac_f(long long num, int den) {
-  long long r = num % den;
-  if (r < 0) r += den;
-  return sinpif((float)(2 * r) / (float)den);
-}
-
-__device__ inline void body_force_f(const Force& f, const Grid& G, int x, int y, int z,
-                                    float F[3]) {
-  F[0] = F[1] = F[2] = 0.f;
-  if (f.kind == 1) {
-    F[0] = f.amp * sin_frac_f((long long)f.k * y, G.ny);
-  } else if (f.kind == 2) {
-    F[0] = f.amp * sin_frac_f((long long)f.k * y, G.ny);
-    F[1] = f.amp * sin_frac_f((long long)f.k * z, G.nz);
-    F[2] = f.amp * sin_frac_f((long long)f.k * x, G.nx);
-  }
-}
-
 // Wave-uniform byte offsets of the rows one 64-node item reads and writes:
 // the start of field b, the plane stride, and the rows y - c_y, z - c_z for
 // c in {-1, 0, 1} (periodic); every population's row is a sum of these.
@@ -540,7 +519,7 @@ __global__ __launch_bounds__(512) void wide_step_kernel(const float* __restrict_
 #pragma unroll
       for (int q = 0; q < Q; ++q) upd[q] = __builtin_fmaf(knn, T[lane * SX + YC + q], upd[q]);
       float F3[3] = {0.f, 0.f, 0.f};
-      if (Fc.kind != 0) body_force_f(Fc, G, t.x, t.y, t.z, F3);
+      if (Fc.kind != 0) body_force(Fc, G, t.x, t.y, t.z, F3);
       float post[Q];
       finish_collision<L>(g, upd, rho, u, F3, Fc.kind != 0, post);
       if (valid && t.active) store_rows<L>(dst, row_offsets(G, Q, t.b, t.y, t.z), t, post);

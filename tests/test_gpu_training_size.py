@@ -110,6 +110,11 @@ def fmt_blocks(be):
     return " ".join(f"[{n:.0e}: {e:.1e}]" for n, e in be)
 
 
+# fp16 is not run here: at this loss scale the adjoint's network operands
+# (dy = s_out / tau x the projected adjoint, about 1e-11) lie below the
+# smallest fp16 subnormal (6e-8) and flush to zero, so the fp16 network's
+# gradient vanishes; bf16 has the float32 exponent range.  fp16 adjoints are
+# checked at unit-scale lam (test_gpu_backward.py).
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_cfg4_unrolled_gradient_8x256(train_case, prec):
     ocfg, g0, ut, theta, T, (xl, xdth, xlam) = train_case
