@@ -506,19 +506,21 @@ struct StepLds {
   static constexpr int min_waves(int prec, bool forced) {
     return (L::Q == 19 && prec != P_F32 && !forced) ? 3 : 1;
   }
-  // wavefronts per workgroup: the unforced 16-bit instances run one
-  // workgroup per compute unit (four wavefronts per SIMD for D2Q9, three for
-  // D3Q19), so that the weights are staged once per compute unit and each
-  // thread stages a quarter as many of them; the others run workgroups of 4
+  // wavefronts per workgroup: the 16-bit D2Q9 instances and the unforced
+  // 16-bit D3Q19 one run one workgroup per compute unit (four wavefronts per
+  // SIMD for D2Q9, three for D3Q19), so that the weights are staged once per
+  // compute unit and each thread stages a quarter as many of them; the
+  // others run workgroups of 4 (the forced 16-bit D3Q19 instance needs 187
+  // registers per lane, and at three wavefronts per SIMD it would spill)
   static constexpr int waves_per_block(int prec, bool forced) {
-    return (prec == P_F32 || forced) ? 4 : (L::Q == 19 ? 12 : 16);
+    return (prec == P_F32 || (forced && L::Q == 19)) ? 4 : (L::Q == 19 ? 12 : 16);
   }
 };
 
 // FORCED: the body force of eq. fext is applied (Force::kind != 0).  The
-// unforced instances leave out the force's registers (its float64 sine and
-// 64-bit argument reduction): 108 instead of 149 registers per lane for the
-// 16-bit D2Q9 instance, 158 instead of 216 for D3Q19.
+// unforced instances leave out the force's registers: 108 instead of 120
+// registers per lane for the 16-bit D2Q9 instance, 159 instead of 187 for
+// D3Q19.
 template <class L, int H, int P, bool FORCED>
 __global__ __launch_bounds__((64 * StepLds<L, H>::waves_per_block(P, FORCED)))
 __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void nlbm_step_kernel(
