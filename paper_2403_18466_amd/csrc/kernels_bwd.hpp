@@ -553,26 +553,32 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
 // workgroup (two per SIMD) take one 16-node group each per step and split
 // the 16 x 16 weight-gradient tiles between them.  After the forward
 // recompute and the backward data path of its group, a wavefront writes the
-// group's gradient operands in contraction layout (the node index as K,
-// 16-bit) to its LDS slot; after a workgroup barrier each wavefront
-// accumulates its own TPW tiles over the 128 nodes of the eight slots.  The
+// group's gradient operands (16-bit, as the products leave them) to its LDS
+// slot; after a workgroup barrier each wavefront reads them back in
+// contraction layout (the node index as K) and accumulates its own TPW
+// tiles over the 128 nodes of the eight slots.  The
 // network weights are read from LDS.  The contraction order is fixed, so
 // the result is reproducible.
 //
-// Slot fragment layout: fragment f holds, for logical lane l = i + 16 g,
-// the four 16-bit values A[i][4 g + r] (feature i of the fragment's 16,
-// nodes 4 g + r of the group) at byte 512 f + 8 slot_pos(swz(l)) + 2 r, with
-// swz(l) = l ^ ((l >> 4) & 3).  The transposing writes from the D layout
-// store two nodes per dword (neighbouring lanes exchange half of their
-// values first).  slot_pos permutes the 8-byte positions within each block
-// of 16 so that every such write puts one lane on each bank, both for 32
-// banks served 32 lanes at a time and for 64 banks served by the whole
-// wavefront; swz alone left two lanes of each 32-lane half on one bank.
-// The 64-bit reads stay conflict-free: each block of 16 positions is still
-// read by 16 consecutive lanes.
-// ---------------------------------------------------------------------------
-__device__ __host__ constexpr int slot_pos(int p) {
-  return p ^ (8 * ((p >> 4) & 1) + (((p >> 4) & 1) ^ ((p >> 5) & 1)));
+// Slot fragment layout: fragment f is 512 bytes, row l (8 bytes) holding the
+// four 16-bit values of lane l of the D-layout tile (features 4 (l / 16) + r
+// of node l % 16), written with one 8-byte store per lane.  The contraction
+// reads it back transposed with ds_read_b64_tr_b16: within each block of 16
+// lanes, lane 4 a + e of the reading wavefront receives element e of the
+// rows that lanes a, a + 4, a + 8 and a + 12 of its block address.  A reading
+// lane L = 16 b + m (a = m % 4, k = m / 4) addresses row 16 a + 4 b + k, and
+// so receives features 4 a + e of node 4 b + k: operand lane L then holds
+// feature L % 16 of nodes 4 (L / 16) + r, the layout the products over the
+// nodes take.
+__device__ __host__ constexpr int tr_row(int L) {
+  return 16 * ((L & 15) & 3) + 4 * (L >> 4) + ((L & 15) >> 2);
+}
+template <int P>
+__device__ inline typename Frag<P>::T read_tr(const unsigned char* p) {
+  typedef short v4s __attribute__((ext_vector_type(4)));
+  const v4s v = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (__attribute__((address_space(3))) v4s*)(p));
+  return __builtin_bit_cast(typename Frag<P>::T, v);
 }
 template <class L, int H, int P>
 struct CoopLayout {
@@ -733,7 +739,7 @@ __device__ inline void coop_tiles(f4 (&acc)[CL::TPW], const unsigned char* slots
   constexpr unsigned one2 = P == P_BF16 ? 0x3F803F80u : 0x3C003C00u;  // two 16-bit 1.0
   const Fr ones = {one2, one2};
   auto frag = [&](int w, int f) {
-    return f < 0 ? ones : *reinterpret_cast<const Fr*>(slots + w * CL::wave_bytes + f * 512 + rdo);
+    return f < 0 ? ones : read_tr<P>(slots + w * CL::wave_bytes + f * 512 + rdo);
   };
 #pragma unroll
   for (int j = 0; j < CL::TPW; ++j) {
@@ -831,19 +837,8 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   unsigned char* slot = mine + CL::soff;
   const unsigned char* slots = wl + CL::soff;  // slot w at w * wave_bytes
 
-  // contraction-layout addresses: this lane's read offset, and the write
-  // offsets of its four D-layout values (feature 4 lg + r, node li)
-  const int rdo = 8 * slot_pos(lane ^ ((lane >> 4) & 3));
-  // A transposed fragment is written two nodes per dword: lanes li and
-  // li ^ 1 swap half of their four values, the even lane then holds
-  // features 0 and 1 of both nodes, the odd lane features 2 and 3.
-  const bool odd = li & 1;
-  int wro[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int r = 2 * (li & 1) + j;
-    wro[j] = 8 * slot_pos(4 * lg + (r ^ (li >> 2)) + 16 * (li >> 2)) + 4 * ((li & 3) >> 1);
-  }
+  // this lane's row of a slot fragment for the transposing reads
+  const int rdo = 8 * tr_row(lane);
 
   // workgroup range of items; wavefront w takes item k + w of each step
   const int nb = gridDim.x, bid = blockIdx.x;
@@ -934,14 +929,8 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
     // the next item's loads are in flight while this item's network runs
     if (k + NW < ib1) load(it + NW, gc, mc);
 
-    auto put_t = [&](int f, Fr v) {
-      const unsigned send = odd ? v[0] : v[1];
-      // quad permutation [1, 0, 3, 2]: every lane receives its neighbour's value
-      const unsigned recv = (unsigned)__builtin_amdgcn_mov_dpp((int)send, 0xB1, 0xF, 0xF, false);
-      const unsigned lo = odd ? recv : v[0], hi = odd ? v[1] : recv;  // even node, odd node
-      *reinterpret_cast<unsigned*>(slot + f * 512 + wro[0]) = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
-      *reinterpret_cast<unsigned*>(slot + f * 512 + wro[1]) = __builtin_amdgcn_perm(hi, lo, 0x07060302u);
-    };
+    // a D-layout fragment to the slot: row l holds lane l's four values
+    auto put_t = [&](int f, Fr v) { *reinterpret_cast<Fr*>(slot + f * 512 + 8 * lane) = v; };
 #pragma unroll 1
     for (int jg = 0; jg < 4; ++jg) {
       const int nrow = 16 * jg + li;
