@@ -556,9 +556,9 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
 // group's gradient operands (16-bit, as the products leave them) to its LDS
 // slot; after a workgroup barrier each wavefront reads them back in
 // contraction layout (the node index as K) and accumulates its own TPW
-// tiles over the 128 nodes of the eight slots.  The
-// network weights are read from LDS.  The contraction order is fixed, so
-// the result is reproducible.
+// tiles over the 128 nodes of the eight slots.  The network weights are
+// staged in LDS once per workgroup and read from there into registers.  The
+// contraction order is fixed, so the result is reproducible.
 //
 // Slot fragment layout: fragment f is 512 bytes, row l (8 bytes) holding the
 // four 16-bit values of lane l of the D-layout tile (features 4 (l / 16) + r
@@ -837,6 +837,27 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   unsigned char* slot = mine + CL::soff;
   const unsigned char* slots = wl + CL::soff;  // slot w at w * wave_bytes
 
+  // Weight fragments in registers: those of layer 2 (W2 and W2^T) always,
+  // the others where two wavefronts per SIMD still hold them (D3Q19 at H = 64
+  // would spill and runs slower); the rest are read from LDS per group.
+  constexpr bool ALLW = CL::NFB + CL::NFF <= 48;
+  constexpr int N1 = S::HB * S::KX, N3 = S::HB * S::QB;
+  Fr w2k[S::HB * S::HB], w2tk[S::HB * S::HB];
+  Fr w1k[ALLW ? N1 : 1], w1tk[ALLW ? N1 : 1], w3tk[ALLW ? N3 : 1];
+#pragma unroll
+  for (int i = 0; i < S::HB * S::HB; ++i) {
+    w2k[i] = W2F[64 * i + lane];
+    w2tk[i] = W2T[64 * i + lane];
+  }
+  if constexpr (ALLW) {
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+      w1k[i] = W1F[64 * i + lane];
+      w1tk[i] = W1T[64 * i + lane];
+    }
+#pragma unroll
+    for (int i = 0; i < N3; ++i) w3tk[i] = W3T[64 * i + lane];
+  }
   // this lane's row of a slot fragment for the transposing reads
   const int rdo = 8 * tr_row(lane);
 
@@ -934,14 +955,18 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll 1
     for (int jg = 0; jg < 4; ++jg) {
       const int nrow = 16 * jg + li;
-      // Each layer's weight fragments are read from LDS as one batch, issued
+      // Weight fragments read from LDS come as one batch per layer, issued
       // before the VALU work of the previous layer so that their latency
       // overlaps it (the scheduling barriers keep the reads there).
       f4 t1[S::HB], t2[S::HB];
       {
-        Fr xin[S::KX], w1[S::HB * S::KX], h1[S::HB], h2[S::HB];
+        Fr xin[S::KX], w1l[ALLW ? 1 : N1], h1[S::HB], h2[S::HB];
+        const Fr* w1 = w1k;
+        if constexpr (!ALLW) {
 #pragma unroll
-        for (int i = 0; i < S::HB * S::KX; ++i) w1[i] = W1F[64 * i + lane];
+          for (int i = 0; i < N1; ++i) w1l[i] = W1F[64 * i + lane];
+          w1 = w1l;
+        }
 #pragma unroll
         for (int c = 0; c < S::KX; ++c) {
           if constexpr (CL::COMPACT) {
@@ -957,9 +982,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob)
           a1[ob] = mma_row<P, S::KX>(f4{0.f, 0.f, 0.f, 0.f}, w1 + ob * S::KX, xin);
-        Fr w2[S::HB * S::HB];
-#pragma unroll
-        for (int i = 0; i < S::HB * S::HB; ++i) w2[i] = W2F[64 * i + lane];
+        const Fr* w2 = w2k;
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob) {
@@ -986,9 +1009,13 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
       }
       {
         // dy in operand layout and in contraction layout
-        Fr dyf[S::QB], w3t[S::HB * S::QB];
+        Fr dyf[S::QB], w3tl[ALLW ? 1 : N3];
+        const Fr* w3t = w3tk;
+        if constexpr (!ALLW) {
 #pragma unroll
-        for (int i = 0; i < S::HB * S::QB; ++i) w3t[i] = W3T[64 * i + lane];
+          for (int i = 0; i < N3; ++i) w3tl[i] = W3T[64 * i + lane];
+          w3t = w3tl;
+        }
 #pragma unroll
         for (int qc = 0; qc < S::QB; ++qc) {
           if constexpr (CL::COMPACT) {
@@ -1005,9 +1032,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob)
           a2[ob] = mma_row<P, S::QB>(f4{0.f, 0.f, 0.f, 0.f}, w3t + ob * S::QB, dyf);
-        Fr w2t[S::HB * S::HB];
-#pragma unroll
-        for (int i = 0; i < S::HB * S::HB; ++i) w2t[i] = W2T[64 * i + lane];
+        const Fr* w2t = w2tk;
         __builtin_amdgcn_sched_barrier(0);
         Fr d2f[S::HB], d1f[S::HB];
 #pragma unroll
@@ -1019,9 +1044,13 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob)
           a3[ob] = mma_row<P, S::HB>(f4{0.f, 0.f, 0.f, 0.f}, w2t + ob * S::HB, d2f);
-        Fr w1t[S::KX * S::HB];
+        Fr w1tl[ALLW ? 1 : N1];
+        const Fr* w1t = w1tk;
+        if constexpr (!ALLW) {
 #pragma unroll
-        for (int i = 0; i < S::KX * S::HB; ++i) w1t[i] = W1T[64 * i + lane];
+          for (int i = 0; i < N1; ++i) w1tl[i] = W1T[64 * i + lane];
+          w1t = w1tl;
+        }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob) {
