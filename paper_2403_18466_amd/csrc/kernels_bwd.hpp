@@ -560,18 +560,21 @@ __global__ __launch_bounds__(256) void nlbm_backward_kernel(
 // staged in LDS once per workgroup and read from there into registers.  The
 // contraction order is fixed, so the result is reproducible.
 //
-// Slot fragment layout: fragment f is 512 bytes, row l (8 bytes) holding the
-// four 16-bit values of lane l of the D-layout tile (features 4 (l / 16) + r
-// of node l % 16), written with one 8-byte store per lane.  The contraction
-// reads it back transposed with ds_read_b64_tr_b16: within each block of 16
-// lanes, lane 4 a + e of the reading wavefront receives element e of the
-// rows that lanes a, a + 4, a + 8 and a + 12 of its block address.  A reading
-// lane L = 16 b + m (a = m % 4, k = m / 4) addresses row 16 a + 4 b + k, and
-// so receives features 4 a + e of node 4 b + k: operand lane L then holds
-// feature L % 16 of nodes 4 (L / 16) + r, the layout the products over the
-// nodes take.
+// Slot fragment layout: fragment f is 512 bytes of 64 rows of 8 bytes; lane
+// l writes its four 16-bit values of the D-layout tile (features 4 (l / 16)
+// + r of node l % 16) to row slot_row(l) = l ^ 4 (l / 16) with one 8-byte
+// store.  The contraction reads it back transposed with ds_read_b64_tr_b16:
+// within each block of 16 lanes, lane 4 a + e of the reading wavefront
+// receives element e of the rows that lanes a, a + 4, a + 8 and a + 12 of
+// its block address.  A reading lane L = 16 b + m (a = m % 4, k = m / 4)
+// addresses the row of writer lane 16 a + 4 b + k, and so receives
+// features 4 a + e of node 4 b + k: operand lane L then holds feature L % 16
+// of nodes 4 (L / 16) + r, the layout the products over the nodes take.
+// The XOR puts the 16 rows that one 16-lane block reads, and those that 16
+// consecutive lanes write, on 16 different bank pairs.
+__device__ __host__ constexpr int slot_row(int l) { return l ^ (4 * (l >> 4)); }
 __device__ __host__ constexpr int tr_row(int L) {
-  return 16 * ((L & 15) & 3) + 4 * (L >> 4) + ((L & 15) >> 2);
+  return slot_row(16 * ((L & 15) & 3) + 4 * (L >> 4) + ((L & 15) >> 2));
 }
 template <int P>
 __device__ inline typename Frag<P>::T read_tr(const unsigned char* p) {
@@ -858,8 +861,8 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll
     for (int i = 0; i < N3; ++i) w3tk[i] = W3T[64 * i + lane];
   }
-  // this lane's row of a slot fragment for the transposing reads
-  const int rdo = 8 * tr_row(lane);
+  // this lane's rows of a slot fragment: written, and read transposed
+  const int wro = 8 * slot_row(lane), rdo = 8 * tr_row(lane);
 
   // workgroup range of items; wavefront w takes item k + w of each step
   const int nb = gridDim.x, bid = blockIdx.x;
@@ -950,8 +953,8 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
     // the next item's loads are in flight while this item's network runs
     if (k + NW < ib1) load(it + NW, gc, mc);
 
-    // a D-layout fragment to the slot: row l holds lane l's four values
-    auto put_t = [&](int f, Fr v) { *reinterpret_cast<Fr*>(slot + f * 512 + 8 * lane) = v; };
+    // a D-layout fragment to the slot: lane l's four values to row slot_row(l)
+    auto put_t = [&](int f, Fr v) { *reinterpret_cast<Fr*>(slot + f * 512 + wro) = v; };
 #pragma unroll 1
     for (int jg = 0; jg < 4; ++jg) {
       const int nrow = 16 * jg + li;
