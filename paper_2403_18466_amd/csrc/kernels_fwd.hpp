@@ -160,16 +160,18 @@ __device__ inline void load_local(rsrc_t src, const Grid& G, const Item& t, floa
 }
 
 // Cache policy bit "nt" (non-temporal) for stores of a state that the next
-// step reads back from HBM anyway; measured faster in the bandwidth-bound
-// BGK step only.
+// step reads back from HBM anyway.  Measured faster in the bandwidth-bound
+// BGK step and in the D2Q9 learned-collision step (0.7% at 4096^2, 5% at
+// 8 x 256^2, where less is left in the L2 to write back when the kernel
+// ends); the adjoint's stores of lambda are faster without it.
 constexpr int kStoreNT = 2;
 
-template <class L>
+template <class L, int POLICY = 0>
 __device__ inline void store_local(rsrc_t dst, const Grid& G, const Item& t, const float v[L::Q]) {
 #pragma unroll
   for (int q = 0; q < L::Q; ++q)
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v[q]), dst, t.vx,
-                                          (int)row_bytes(G, L::Q, t.b, q, t.z, t.y), 0);
+                                          (int)row_bytes(G, L::Q, t.b, q, t.z, t.y), POLICY);
 }
 
 template <class L, int q = 0>
@@ -654,7 +656,7 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
     if constexpr (FORCED) body_force(Fc, G, t.x, t.y, t.z, F3);
     float post[Q];
     finish_collision<L>(g, upd, rho, u, F3, FORCED, post);
-    if (t.active) store_local<L>(dst, G, t, post);
+    if (t.active) store_local<L, kStoreNT>(dst, G, t, post);
     wave_lds_sync();
     cur = nxt;
   }
