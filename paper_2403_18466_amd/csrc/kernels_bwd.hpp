@@ -840,26 +840,25 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   unsigned char* slot = mine + CL::soff;
   const unsigned char* slots = wl + CL::soff;  // slot w at w * wave_bytes
 
-  // Weight fragments in registers: those of layer 2 (W2 and W2^T) always,
-  // the others where two wavefronts per SIMD still hold them (D3Q19 at H = 64
-  // would spill and runs slower); the rest are read from LDS per group.
-  constexpr bool ALLW = CL::NFB + CL::NFF <= 48;
+  // Weight fragments in registers: all of them where two wavefronts per SIMD
+  // hold them (the D2Q9 networks, 256 registers at H = 64); else all but W1,
+  // which is then read from LDS per group (D3Q19 at H = 64: 256 registers;
+  // W1 as well spills and runs slower, and of the four sets it gains least).
+  constexpr bool RW1 = CL::NFB + CL::NFF <= 48;
   constexpr int N1 = S::HB * S::KX, N3 = S::HB * S::QB;
-  Fr w2k[S::HB * S::HB], w2tk[S::HB * S::HB];
-  Fr w1k[ALLW ? N1 : 1], w1tk[ALLW ? N1 : 1], w3tk[ALLW ? N3 : 1];
+  Fr w2k[S::HB * S::HB], w2tk[S::HB * S::HB], w1tk[N1], w3tk[N3], w1k[RW1 ? N1 : 1];
 #pragma unroll
   for (int i = 0; i < S::HB * S::HB; ++i) {
     w2k[i] = W2F[64 * i + lane];
     w2tk[i] = W2T[64 * i + lane];
   }
-  if constexpr (ALLW) {
 #pragma unroll
-    for (int i = 0; i < N1; ++i) {
-      w1k[i] = W1F[64 * i + lane];
-      w1tk[i] = W1T[64 * i + lane];
-    }
+  for (int i = 0; i < N1; ++i) w1tk[i] = W1T[64 * i + lane];
 #pragma unroll
-    for (int i = 0; i < N3; ++i) w3tk[i] = W3T[64 * i + lane];
+  for (int i = 0; i < N3; ++i) w3tk[i] = W3T[64 * i + lane];
+  if constexpr (RW1) {
+#pragma unroll
+    for (int i = 0; i < N1; ++i) w1k[i] = W1F[64 * i + lane];
   }
   // this lane's rows of a slot fragment: written, and read transposed
   const int wro = 8 * slot_row(lane), rdo = 8 * tr_row(lane);
@@ -963,9 +962,9 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
       // overlaps it (the scheduling barriers keep the reads there).
       f4 t1[S::HB], t2[S::HB];
       {
-        Fr xin[S::KX], w1l[ALLW ? 1 : N1], h1[S::HB], h2[S::HB];
+        Fr xin[S::KX], w1l[RW1 ? 1 : N1], h1[S::HB], h2[S::HB];
         const Fr* w1 = w1k;
-        if constexpr (!ALLW) {
+        if constexpr (!RW1) {
 #pragma unroll
           for (int i = 0; i < N1; ++i) w1l[i] = W1F[64 * i + lane];
           w1 = w1l;
@@ -1012,13 +1011,8 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
       }
       {
         // dy in operand layout and in contraction layout
-        Fr dyf[S::QB], w3tl[ALLW ? 1 : N3];
+        Fr dyf[S::QB];
         const Fr* w3t = w3tk;
-        if constexpr (!ALLW) {
-#pragma unroll
-          for (int i = 0; i < N3; ++i) w3tl[i] = W3T[64 * i + lane];
-          w3t = w3tl;
-        }
 #pragma unroll
         for (int qc = 0; qc < S::QB; ++qc) {
           if constexpr (CL::COMPACT) {
@@ -1047,13 +1041,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob)
           a3[ob] = mma_row<P, S::HB>(f4{0.f, 0.f, 0.f, 0.f}, w2t + ob * S::HB, d2f);
-        Fr w1tl[ALLW ? 1 : N1];
         const Fr* w1t = w1tk;
-        if constexpr (!ALLW) {
-#pragma unroll
-          for (int i = 0; i < N1; ++i) w1tl[i] = W1T[64 * i + lane];
-          w1t = w1tl;
-        }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob) {
