@@ -504,9 +504,11 @@ struct StepLds {
   // (row 4 ob + g holds b3[16 ob + 4 g .. + 3]), not in registers
   static constexpr int B3 = YC + YQ;
   // wavefronts per SIMD the compiler must leave room for: three for the
-  // unforced 16-bit D3Q19 instances, else no constraint
+  // unforced 16-bit D3Q19 instances and the unforced fp32 D2Q9 one (which
+  // the max-ILP scheduler otherwise takes to two: 8% slower), else no
+  // constraint
   static constexpr int min_waves(int prec, bool forced) {
-    return (L::Q == 19 && prec != P_F32 && !forced) ? 3 : 1;
+    return (!forced && ((L::Q == 19 && prec != P_F32) || (L::Q == 9 && prec == P_F32))) ? 3 : 1;
   }
   // wavefronts per workgroup: the 16-bit D2Q9 instances and the unforced
   // 16-bit D3Q19 one run one workgroup per compute unit (four wavefronts per
@@ -661,5 +663,25 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
     cur = nxt;
   }
 }
+
+// Workgroups for a persistent kernel: as many as fit on the chip at once
+// (occ per compute unit), no more than there are work units, a multiple of
+// the 8 XCDs when large.
+inline unsigned persistent_grid(int ncu, int occ, long long units_per_block_min,
+                                long long units) {
+  if (occ < 1) occ = 1;
+  long long want = (long long)ncu * occ;
+  long long cap = (units + units_per_block_min - 1) / units_per_block_min;
+  long long nb = want < cap ? want : cap;
+  if (nb >= 16) nb -= nb % 8;
+  if (nb < 1) nb = 1;
+  return (unsigned)nb;
+}
+
+// Launch of the learned-collision step for (lattice, H, precision, forcing),
+// defined in nlbm_fwd.hip: a persistent grid over the nitems 64-node items.
+hipError_t nlbm_fwd_launch(bool d3q19, int hidden, int prec, bool forced, int ncu, hipStream_t s,
+                           const float* Ain, float* Aout, const float* theta, Grid G, Force Fc,
+                           float rho0, float omega, float knn, int nitems, int nxc);
 
 }  // namespace lbm

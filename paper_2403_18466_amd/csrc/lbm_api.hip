@@ -354,24 +354,12 @@ lbm_status launch_bgk(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t s
   return launch_bgk_v<L, 1, true, false>(ctx, Ain, Aout, s);
 }
 
-// Workgroups for a persistent kernel: as many as fit on the chip at once,
-// no more than there are work units, a multiple of the 8 XCDs when large.
-template <class K>
-lbm_status persistent_blocks(lbm_ctx* ctx, K kernel, int threads, long long units_per_block_min,
-                             long long units, unsigned& blocks) {
-  int occ = 0;
-  LBM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0));
-  if (occ < 1) occ = 1;
-  long long want = (long long)ctx->ncu * occ;
-  long long cap = (units + units_per_block_min - 1) / units_per_block_min;
-  long long nb = want < cap ? want : cap;
-  if (nb >= 16) nb -= nb % 8;
-  if (nb < 1) nb = 1;
-  blocks = (unsigned)nb;
-  return LBM_OK;
+int prec_of(int mlp_prec) {
+  return mlp_prec == LBM_MLP_FP32 ? P_F32 : (mlp_prec == LBM_MLP_BF16 ? P_BF16 : P_F16);
 }
 
-template <class L, int H, int P>
+// The learned-collision step: its instances live in nlbm_fwd.hip.
+template <class L, int H>
 lbm_status launch_nlbm(lbm_ctx* ctx, const float* Ain, float* Aout, const float* theta,
                        hipStream_t s) {
   Grid G = grid_of(ctx->cfg);
@@ -379,35 +367,16 @@ lbm_status launch_nlbm(lbm_ctx* ctx, const float* Ain, float* Aout, const float*
   long long nitems = (long long)nxc * G.ny * G.nz * G.batch;
   if (nitems >= (1LL << 31)) return fail(LBM_ERR_INVALID, "too many work items");
   const lbm_config& c = ctx->cfg;
-  // forced and unforced instances: the unforced one needs fewer registers
-  const bool forced = c.force_kind != LBM_FORCE_NONE;
-  const auto kernel = forced ? nlbm_step_kernel<L, H, P, true> : nlbm_step_kernel<L, H, P, false>;
-  const int wb = StepLds<L, H>::waves_per_block(P, forced);
-  unsigned blocks = 0;
-  lbm_status st = persistent_blocks(ctx, kernel, 64 * wb, wb, nitems, blocks);
-  if (st != LBM_OK) return st;
-  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(64 * wb), 0, s, Ain, Aout, theta, G, force_of(ctx),
-                     (float)c.rho0, (float)(1.0 / c.tau), (float)(c.out_scale / c.tau),
-                     (int)nitems, nxc);
-  LBM_LAUNCHED("nlbm_step_kernel");
+  hipError_t e = nlbm_fwd_launch(L::Q == 19, H, prec_of(c.mlp_prec),
+                                 c.force_kind != LBM_FORCE_NONE, ctx->ncu, s, Ain, Aout, theta, G,
+                                 force_of(ctx), (float)c.rho0, (float)(1.0 / c.tau),
+                                 (float)(c.out_scale / c.tau), (int)nitems, nxc);
+  if (e != hipSuccess)
+    return fail(LBM_ERR_HIP, std::string("launch of nlbm_step_kernel: ") + hipGetErrorString(e));
   return LBM_OK;
 }
 
-template <class L, int H>
-lbm_status launch_nlbm_p(lbm_ctx* ctx, const float* Ain, float* Aout, const float* theta,
-                         hipStream_t s) {
-  switch (ctx->cfg.mlp_prec) {
-    case LBM_MLP_FP32: return launch_nlbm<L, H, P_F32>(ctx, Ain, Aout, theta, s);
-    case LBM_MLP_BF16: return launch_nlbm<L, H, P_BF16>(ctx, Ain, Aout, theta, s);
-    default: return launch_nlbm<L, H, P_F16>(ctx, Ain, Aout, theta, s);
-  }
-}
-
 // The wide network: weights into fragment order, then the persistent step.
-int prec_of(int mlp_prec) {
-  return mlp_prec == LBM_MLP_FP32 ? P_F32 : (mlp_prec == LBM_MLP_BF16 ? P_BF16 : P_F16);
-}
-
 lbm_status wide_pack(lbm_ctx* ctx, const float* theta, hipStream_t s) {
   const int n = ctx->wide_nw + ctx->wide_nb;
   hipError_t e = wide_pack_launch(prec_of(ctx->cfg.mlp_prec), blocks_for(n), s, theta,
@@ -451,8 +420,8 @@ lbm_status one_step(lbm_ctx* ctx, const float* Ain, float* Aout, const float* th
   }
   switch (ctx->cfg.hidden) {
     case 0: return launch_bgk<L>(ctx, Ain, Aout, s);
-    case 32: return launch_nlbm_p<L, 32>(ctx, Ain, Aout, theta, s);
-    default: return launch_nlbm_p<L, 64>(ctx, Ain, Aout, theta, s);
+    case 32: return launch_nlbm<L, 32>(ctx, Ain, Aout, theta, s);
+    default: return launch_nlbm<L, 64>(ctx, Ain, Aout, theta, s);
   }
 }
 
