@@ -1122,6 +1122,55 @@ static __global__ __launch_bounds__(1024) void grad_reduce_kernel(const float* _
   }
 }
 
+// Launch of the adjoint kernel for (lattice, H, precision): the instances of
+// each lattice are built in a translation unit of their own (nlbm_bwd.hip
+// for D3Q19, nlbm_bwd_d2q9.hip for D2Q9), with their own scheduler options.
+namespace bwd_detail {
+
+template <class L, int H, int P>
+hipError_t bwd_one(unsigned blocks, hipStream_t s, const float* A, const float* theta,
+                   const float* lam1, float* lam0, float* part, Grid G, Force Fc, float rho0,
+                   float omega, float knn, int nitems, int nxc, int accum) {
+  if constexpr (CoopLayout<L, H, P>::ok)
+    hipLaunchKernelGGL((nlbm_backward_coop_kernel<L, H, P>), dim3(blocks),
+                       dim3(64 * CoopLayout<L, H, P>::NW), 0, s, A,
+                       theta, lam1, lam0, part, G, Fc, rho0, omega, knn, nitems, nxc, accum);
+  else
+    hipLaunchKernelGGL((nlbm_backward_kernel<L, H, P>), dim3(blocks), dim3(256), 0, s, A, theta,
+                       lam1, lam0, part, G, Fc, rho0, omega, knn, nitems, nxc, accum);
+  return hipGetLastError();
+}
+
+template <class L, int H>
+hipError_t bwd_prec(int prec, unsigned blocks, hipStream_t s, const float* A, const float* theta,
+                    const float* lam1, float* lam0, float* part, Grid G, Force Fc, float rho0,
+                    float omega, float knn, int nitems, int nxc, int accum) {
+  switch (prec) {
+    case P_F32:
+      return bwd_one<L, H, P_F32>(blocks, s, A, theta, lam1, lam0, part, G, Fc, rho0, omega, knn, nitems, nxc, accum);
+    case P_BF16:
+      return bwd_one<L, H, P_BF16>(blocks, s, A, theta, lam1, lam0, part, G, Fc, rho0, omega, knn, nitems, nxc, accum);
+    default:
+      return bwd_one<L, H, P_F16>(blocks, s, A, theta, lam1, lam0, part, G, Fc, rho0, omega, knn, nitems, nxc, accum);
+  }
+}
+
+template <class L>
+hipError_t bwd_hidden(int hidden, int prec, unsigned blocks, hipStream_t s, const float* A,
+                      const float* theta, const float* lam1, float* lam0, float* part, Grid G,
+                      Force Fc, float rho0, float omega, float knn, int nitems, int nxc, int accum) {
+  if (hidden == 32)
+    return bwd_prec<L, 32>(prec, blocks, s, A, theta, lam1, lam0, part, G, Fc, rho0, omega, knn, nitems, nxc, accum);
+  return bwd_prec<L, 64>(prec, blocks, s, A, theta, lam1, lam0, part, G, Fc, rho0, omega, knn, nitems, nxc, accum);
+}
+
+}  // namespace bwd_detail
+
+hipError_t nlbm_bwd_launch_d2q9(int hidden, int prec, unsigned blocks, hipStream_t s,
+                                const float* A, const float* theta, const float* lam1,
+                                float* lam0, float* part, Grid G, Force Fc, float rho0,
+                                float omega, float knn, int nitems, int nxc, int accum);
+
 // Launch of the adjoint kernel for (lattice, H, precision), defined in
 // nlbm_bwd.hip.  Each workgroup writes its partial gradient to its row of
 // part (accum = 0) or adds it to what the row holds (accum = 1, for the
