@@ -473,8 +473,9 @@ def cpu_baseline():
       field (same network, tau, initial recipe, periodic in both directions):
       the per-node work of the headline workload, bounded to about 10 s;
     * the 64^2 parity workload in full (500 steps, 9->32->32->9);
-    * context: 2 steps of the full 4096^2 headline field with the oracle's
-      row-parallel loops on all host CPUs this process may use."""
+    * context: 2 steps of the full 4096^2 headline field, and the first 20
+      steps of the 1024^2 Kolmogorov workload, with the oracle's row-parallel
+      loops on all host CPUs this process may use."""
     import numpy as np
 
     import oracle
@@ -504,6 +505,14 @@ def cpu_baseline():
     t2 = time.perf_counter()
     oracle.run(full, g, theta, 2)
     d2 = time.perf_counter() - t2
+    # all host threads: the first 20 steps of the 1024^2 Kolmogorov workload
+    kc = oracle.Config(nx=1024, ny=1024, tau=TAU, hidden=HIDDEN, out_scale=S_OUT, force_kind=1,
+                       force_amp=1e-5, force_k=4)
+    uk = inputs.fourier_modes_velocity(1024, 1024, kmax=4, umax=0.01, seed=0)
+    gk = oracle.init_equilibrium(kc, np.ones((1, 1, 1024, 1024)), uk[None, :, None])
+    t3 = time.perf_counter()
+    oracle.run(kc, gk, theta, 20)
+    d3 = time.perf_counter() - t3
     oracle.set_threads(1)
     return {"value": value, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"2 steps of a {N}x{rows} strip of the headline field (same network, "
@@ -514,6 +523,8 @@ def cpu_baseline():
                                         "mlups": 64 * 64 * 500 / d1 / 1e6, "threads": 1},
             "headline_4096_two_steps_all_threads": {"threads": nt, "s": d2,
                                                     "mlups": N * N * 2 / d2 / 1e6},
+            "kolmogorov_1024_20_steps_all_threads": {"threads": nt, "s": d3,
+                                                     "mlups": 1024 * 1024 * 20 / d3 / 1e6},
             "rows": oracle_rows()}
 
 
