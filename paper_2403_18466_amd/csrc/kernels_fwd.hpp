@@ -493,16 +493,23 @@ __device__ inline void wave_lds_sync() {
 template <class L, int H>
 struct StepLds {
   // One row per node: the network input (g, the constant 1 of the layer-1
-  // bias, zeros up to YC), then the network output y (YQ columns), then 4
-  // columns of padding.  Input columns past YC are read as zeros without
-  // being stored.
+  // bias, zeros up to YC), then the network output y (YQ columns from YO),
+  // then 4 columns of padding.  Layer 1 reads 16 KX input columns: where the
+  // LDS allows (D2Q9) the columns from YC to YO = 16 KX are stored zeros, so
+  // that the read needs no masking; else (D3Q19) YO = YC and the input
+  // columns past YC are read as zeros without being stored.  A row stride
+  // that is a multiple of 32 floats would put every row on the same banks.
   static constexpr int YC = (L::Q + 1 + 3) / 4 * 4;
   static constexpr int YQ = (L::Q + 3) / 4 * 4;
-  static constexpr int SX = YC + YQ + 4;  // row stride (floats)
+  static constexpr int ZC = 16 * ((L::Q + 1 + 15) / 16);  // input columns layer 1 reads
+  static constexpr int YO = L::Q == 9 ? ZC : YC;
+  static constexpr bool ZERO_PAD = YO >= ZC;
+  static constexpr int SX0 = YO + YQ + 4;
+  static constexpr int SX = SX0 % 32 == 0 ? SX0 + 4 : SX0;  // row stride (floats)
   static constexpr int per_wave = 64 * SX;
   // the layer-3 bias sits in the padding columns of the first 4 QB rows
   // (row 4 ob + g holds b3[16 ob + 4 g .. + 3]), not in registers
-  static constexpr int B3 = YC + YQ;
+  static constexpr int B3 = YO + YQ;
   // wavefronts per SIMD the compiler must leave room for: three for the
   // unforced 16-bit D3Q19 instances and the unforced fp32 D2Q9 one (which
   // the max-ILP scheduler otherwise takes to two: 8% slower), else no
@@ -541,7 +548,7 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, lg = lane >> 4, li = lane & 15;
   float* X = lds + wave * LD::per_wave;
-  float* Y = X + LD::YC;  // output columns of the same rows
+  float* Y = X + LD::YO;  // output columns of the same rows
 
   const int nb = gridDim.x, bid = blockIdx.x;
   const int lb = (nb % 8 == 0) ? (bid % 8) * (nb / 8) + bid / 8 : bid;
@@ -594,7 +601,7 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
   // the input columns past the populations never change: a constant 1 for
   // the bias of layer 1, then zeros
 #pragma unroll
-  for (int k = Q; k < LD::YC; ++k) X[lane * LD::SX + k] = k == Q ? 1.f : 0.f;
+  for (int k = Q; k < LD::YO; ++k) X[lane * LD::SX + k] = k == Q ? 1.f : 0.f;
   if (lane < 4 * S::QB) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -625,8 +632,13 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
 #pragma unroll
       for (int c = 0; c < S::KX; ++c) {
         const int col = 16 * c + 4 * lg;
-        f4 v = *reinterpret_cast<const f4*>(X + nrow * LD::SX + (col < LD::YC ? col : 0));
-        if (col >= LD::YC) v = f4{0.f, 0.f, 0.f, 0.f};
+        f4 v;
+        if constexpr (LD::ZERO_PAD) {
+          v = *reinterpret_cast<const f4*>(X + nrow * LD::SX + col);
+        } else {
+          v = *reinterpret_cast<const f4*>(X + nrow * LD::SX + (col < LD::YC ? col : 0));
+          if (col >= LD::YC) v = f4{0.f, 0.f, 0.f, 0.f};
+        }
         xin[c] = to_frag<P>(v);
       }
       F h1[S::HB], h2[S::HB];
