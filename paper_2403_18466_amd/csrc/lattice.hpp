@@ -151,7 +151,8 @@ struct Unroll {
         geq[q] = L::w[q] * __builtin_fmaf(rho, -1.5f * uu, drho);
       } else {
         float cu = cdot<L, q>(u);
-        float p = __builtin_fmaf(4.5f * cu, cu, __builtin_fmaf(3.f, cu, -1.5f * uu));
+        // 3 cu + 9/2 cu^2 - 3/2 |u|^2 as cu (3 + 9/2 cu) - 3/2 |u|^2: two FMAs
+        float p = __builtin_fmaf(cu, __builtin_fmaf(4.5f, cu, 3.f), -1.5f * uu);
         geq[q] = L::w[q] * __builtin_fmaf(rho, p, drho);
       }
       Unroll<L, q + 1>::feq(drho, rho, u, uu, geq);
