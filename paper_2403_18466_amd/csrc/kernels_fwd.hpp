@@ -106,6 +106,21 @@ struct ItemWalk {
       }
     }
   }
+  // s items further on (s >= 0); the carry loop runs floor((xc + s) / nxc)
+  // times
+  __device__ inline void advance(int s, int nxc, const Grid& G) {
+    xc += s;
+    while (xc >= nxc) {
+      xc -= nxc;
+      if (++y == G.ny) {
+        y = 0;
+        if (++z == G.nz) {
+          z = 0;
+          ++b;
+        }
+      }
+    }
+  }
   // Lane addressing; lanes past the end of the row read node nx - 1 (their
   // results are never stored).
   __device__ inline Item item(const Grid& G, int lane, int W = 64) const {
