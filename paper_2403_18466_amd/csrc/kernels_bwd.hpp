@@ -596,6 +596,44 @@ struct CoopLayout {
   static constexpr int R = S::HB + 1;
   static constexpr int NT2 = S::HB * R, NT1 = S::HB * S::KX, NT3 = S::QB * R;
   static constexpr int NT = NT2 + NT1 + NT3, TPW = (NT + NW - 1) / NW;
+  // Tile j of wavefront W (-1: none).  At H = 64 a wavefront's tiles share
+  // their operands: 2 x 2 blocks of dW2 (D3Q19: with the b2 tile of one of
+  // the block's rows), the b2 tiles together (D2Q9), blocks of dW1 and of
+  // dW3 with b3.  Per 16-node step the eight wavefronts then read 248
+  // (D2Q9) or 256 (D3Q19) operand fragments from the slots instead of the
+  // 280 and 328 of consecutive tiles.  Other shapes take consecutive tiles.
+  static constexpr int tile(int W, int j) {
+    if constexpr (S::HB == 4 && S::KX == 1 && S::QB == 1 && TPW == 4) {
+      constexpr int m[8][4] = {{0, 1, 5, 6},     {2, 3, 7, 8},     {10, 11, 15, 16},
+                               {12, 13, 17, 18}, {4, 9, 14, 19},   {20, 21, 22, 23},
+                               {24, 25, 26, 28}, {27, -1, -1, -1}};
+      return m[W][j];
+    } else if constexpr (S::HB == 4 && S::KX == 2 && S::QB == 2 && TPW == 5) {
+      constexpr int m[8][5] = {{0, 1, 5, 6, 4},       {2, 3, 7, 8, 9},
+                               {10, 11, 15, 16, 14},  {12, 13, 17, 18, 19},
+                               {20, 21, 22, 23, -1},  {24, 25, 26, 27, -1},
+                               {28, 29, 33, 34, 32},  {30, 31, 35, 36, 37}};
+      return m[W][j];
+    } else {
+      return W * TPW + j < NT ? W * TPW + j : -1;
+    }
+  }
+  // loop order of the tile products: slot pairs outer for D3Q19, tiles
+  // outer for D2Q9 (the other order spills registers in each)
+  static constexpr bool PAIRS_OUTER = L::Q != 9;
+  // every tile belongs to exactly one wavefront
+  static constexpr bool tiles_ok() {
+    int seen[NT] = {};
+    for (int W = 0; W < NW; ++W)
+      for (int j = 0; j < TPW; ++j) {
+        const int t = tile(W, j);
+        if (t >= NT || t < -1) return false;
+        if (t >= 0 && seen[t]++) return false;
+      }
+    for (int t = 0; t < NT; ++t)
+      if (!seen[t]) return false;
+    return true;
+  }
   // fragments of one group, in slot order
   static constexpr int FDY = 0, FH2 = FDY + S::QB, FD2 = FH2 + S::HB, FH1 = FD2 + S::HB,
                        FD1 = FH1 + S::HB, FX0 = FD1 + S::HB, NFR = FX0 + S::KX;
@@ -734,8 +772,11 @@ __device__ inline void stage_adjoint_weights(typename Frag<P>::T* bwd, typename 
   __syncthreads();
 }
 
-// acc[j] += the product of tile W TPW + j over the slots (the nodes of
-// slots 2p and 2p + 1 form the K = 32 of one matrix-core instruction).
+// acc[j] += the product of tile CL::tile(W, j) over the slots (the nodes of
+// slots 2p and 2p + 1 form the K = 32 of one matrix-core instruction).  The
+// slot pairs are the outer loop, so an operand fragment that several of the
+// wavefront's tiles use is read once per pair; each tile still sums the
+// pairs in slot order.
 template <class CL, int P, int W>
 __device__ inline void coop_tiles(f4 (&acc)[CL::TPW], const unsigned char* slots, int rdo) {
   using Fr = typename Frag<P>::T;
@@ -744,15 +785,22 @@ __device__ inline void coop_tiles(f4 (&acc)[CL::TPW], const unsigned char* slots
   auto frag = [&](int w, int f) {
     return f < 0 ? ones : read_tr<P>(slots + w * CL::wave_bytes + f * 512 + rdo);
   };
+  auto pair = [&](int j, int p) {
+    const int t = CL::tile(W, j);
+    if (t >= 0)
+      acc[j] = mma_pair<P>(acc[j], frag(p, CL::fa(t)), frag(p + 1, CL::fa(t)),
+                           frag(p, CL::fb(t)), frag(p + 1, CL::fb(t)));
+  };
+  if constexpr (CL::PAIRS_OUTER) {
 #pragma unroll
-  for (int j = 0; j < CL::TPW; ++j) {
-    const int t = W * CL::TPW + j;
-    if (t < CL::NT) {
+    for (int p = 0; p < CL::NW; p += 2)
 #pragma unroll
-      for (int p = 0; p < CL::NW; p += 2)
-        acc[j] = mma_pair<P>(acc[j], frag(p, CL::fa(t)), frag(p + 1, CL::fa(t)),
-                             frag(p, CL::fb(t)), frag(p + 1, CL::fb(t)));
-    }
+      for (int j = 0; j < CL::TPW; ++j) pair(j, p);
+  } else {
+#pragma unroll
+    for (int j = 0; j < CL::TPW; ++j)
+#pragma unroll
+      for (int p = 0; p < CL::NW; p += 2) pair(j, p);
   }
 }
 
@@ -763,8 +811,8 @@ __device__ inline void coop_put(const f4 (&acc)[CL::TPW], float* red, int lg, in
   using S = typename CL::S;
 #pragma unroll
   for (int j = 0; j < CL::TPW; ++j) {
-    const int t = W * CL::TPW + j;
-    if (t >= CL::NT) continue;
+    const int t = CL::tile(W, j);
+    if (t < 0) continue;
     const int a = 16 * CL::row(t) + 4 * lg, b = 16 * CL::col(t) + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -815,6 +863,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   using Fr = typename Frag<P>::T;
   constexpr int Q = L::Q, NW = CL::NW;
   static_assert(CL::ok, "cooperative adjoint: precision or LDS budget");
+  static_assert(CL::tiles_ok(), "cooperative adjoint: tile assignment");
   __shared__ Fr wts[(CL::NFB + CL::NFF) * 64];
   __shared__ __attribute__((aligned(16))) float b2s[H];  // c b2 (the layer-2 bias)
   __shared__ __attribute__((aligned(16))) unsigned char wl[NW * CL::wave_bytes];
