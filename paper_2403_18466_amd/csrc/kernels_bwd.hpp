@@ -925,13 +925,12 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * Q) * 4u;
   const rsrc_t rA = make_rsrc(A, bytes), rL1 = make_rsrc(lam1, bytes),
                rL0 = make_rsrc(lam0, bytes);
-  constexpr bool WALK = L::Q == 9;
   // items past the range enter as zeros: every product they feed is zero
   auto load = [&](int it, const ItemWalk& w, float g[Q], float mu[Q]) {
     bool act = false;
     Item t;
     if (it < ib1) {
-      t = WALK ? w.item(G, lane) : locate_item(it, nxc, G, lane);
+      t = w.item(G, lane);
       act = t.active;
     }
     if (act) {
@@ -943,17 +942,16 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
     }
   };
 
-  // The wavefront's items are NW apart.  D2Q9 walks them without integer
+  // The wavefront's items are NW apart: they are walked without integer
   // division (one decode per launch; an item past the range keeps its walked
-  // position and loads and stores nothing): 1.7% faster at 1024^2 x 4.
-  // D3Q19 decodes each item (the walk measured 1.3% slower at 256^3).
+  // position and loads and stores nothing).
   ItemWalk wcur, wnxt;
-  if constexpr (WALK) wcur.start(ib0 + wave, nxc, G);
+  wcur.start(ib0 + wave, nxc, G);
   float gc[Q], mc[Q];
   if (ib0 < ib1) load(ib0 + wave, wcur, gc, mc);
   for (int k = ib0; k < ib1; k += NW) {
     const int it = k + wave;
-    const Item t = WALK ? wcur.item(G, lane) : locate_item(it < ib1 ? it : ib0, nxc, G, lane);
+    const Item t = wcur.item(G, lane);
     const bool act = it < ib1 && t.active;
     float F3[3] = {0.f, 0.f, 0.f};
     if (Fc.kind != 0) body_force(Fc, G, t.x, t.y, t.z, F3);
@@ -1006,10 +1004,8 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
     }
     wave_lds_sync();
     // the next item's loads are in flight while this item's network runs
-    if constexpr (WALK) {
-      wnxt = wcur;
-      wnxt.advance(NW, nxc, G);
-    }
+    wnxt = wcur;
+    wnxt.advance(NW, nxc, G);
     if (k + NW < ib1) load(it + NW, wnxt, gc, mc);
 
     // a D-layout fragment to the slot: lane l's four values to row slot_row(l)
@@ -1142,7 +1138,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
     }
     if (act) scatter_item<L>(rL0, G, t, lam);
     wave_lds_sync();
-    if constexpr (WALK) wcur = wnxt;
+    wcur = wnxt;
   }
 
   // Partial gradient of the workgroup: the tiles are disjoint between the
