@@ -19,9 +19,9 @@ LIB = os.path.join(PKG, "liblbm_hip.so")
 VGPR_FORM = ("-mllvm", "-amdgpu-mfma-vgpr-form")
 # max-ILP instruction scheduler: the learned-collision step ran 1% faster with
 # it on every grid measured (D2Q9 8 x 256^2 to 4096^2, D3Q19 256^3), the D2Q9
-# adjoint 1.5% faster; the D3Q19 adjoint stays on the default scheduler (2%
-# slower with it), and so do the other kernels, several of which need more
-# registers with it
+# adjoint 1.5% faster, the D3Q19 adjoint 1.9% (since its gradient tiles share
+# operands; 2% slower before); the other kernels stay on the default
+# scheduler, several of which need more registers with it
 MAX_ILP = ("-mllvm", "-amdgpu-sched-strategy=max-ilp")
 # (source, extra flags): the wide-network kernels use the max-ILP scheduler
 # too, which keeps their LDS weight reads ahead of the matrix-core work,
@@ -32,7 +32,7 @@ SOURCES = [
     # canonicalisation; the wide step has no NaN tests)
     (os.path.join(CSRC, "wide.hip"), VGPR_FORM + MAX_ILP + ("-mno-amdgpu-ieee", "-fno-honor-nans")),
     (os.path.join(CSRC, "wide_bwd.hip"), VGPR_FORM),
-    (os.path.join(CSRC, "nlbm_bwd.hip"), VGPR_FORM),
+    (os.path.join(CSRC, "nlbm_bwd.hip"), VGPR_FORM + MAX_ILP),
     (os.path.join(CSRC, "nlbm_bwd_d2q9.hip"), VGPR_FORM + MAX_ILP),
 ]
 
