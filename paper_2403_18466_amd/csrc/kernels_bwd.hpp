@@ -934,8 +934,9 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
       act = t.active;
     }
     if (act) {
-      gather_item<L>(rA, G, t, g);
-      load_local<L>(rL1, G, t, mu);
+      const ItemRows r(G, Q, t);
+      gather_rows<L>(rA, r, t, g);
+      load_rows<L>(rL1, r, t, mu);
     } else {
 #pragma unroll
       for (int q = 0; q < Q; ++q) g[q] = mu[q] = 0.f;
@@ -1136,7 +1137,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll
       for (int q = 0; q < Q; ++q) lam[q] += D[lane * CL::SD + q];
     }
-    if (act) scatter_item<L>(rL0, G, t, lam);
+    if (act) scatter_rows<L>(rL0, ItemRows(G, Q, t), t, lam);
     wave_lds_sync();
     wcur = wnxt;
   }

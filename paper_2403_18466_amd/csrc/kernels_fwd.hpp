@@ -154,6 +154,60 @@ __device__ inline void pull_offsets(const Grid& G, const Item& t, unsigned& so, 
   vo = L::cx[q] > 0 ? t.vm : (L::cx[q] < 0 ? t.vp : t.vx);
 }
 
+// The rows of an item, for kernels that read and write them several times:
+// row (zs, ys) of plane q of the item's field starts at byte
+//   base + q plane + z[1 - dz] + y[1 - dy],  zs = z - dz, ys = y - dy (periodic),
+// the same sum as row_bytes; every term is wave-uniform.
+struct ItemRows {
+  unsigned base, plane, y[3], z[3];
+  __device__ inline ItemRows(const Grid& G, int Q, const Item& t) {
+    const unsigned row = (unsigned)G.nx * 4u, slab = row * (unsigned)G.ny;
+    plane = slab * (unsigned)G.nz;
+    base = (unsigned)(t.b * Q) * plane;
+    y[0] = (unsigned)wrap_sub(t.y, 1, G.ny) * row;
+    y[1] = (unsigned)t.y * row;
+    y[2] = (unsigned)wrap_sub(t.y, -1, G.ny) * row;
+    z[0] = (unsigned)wrap_sub(t.z, 1, G.nz) * slab;
+    z[1] = (unsigned)t.z * slab;
+    z[2] = (unsigned)wrap_sub(t.z, -1, G.nz) * slab;
+  }
+};
+
+// gather_item, load_local and scatter_item with the rows of an ItemRows.
+template <class L>
+__device__ inline void gather_rows(rsrc_t src, const ItemRows& r, const Item& t, float g[L::Q]) {
+  unsigned qo = r.base;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const unsigned so = qo + (r.z[1 - L::cz[q]] + r.y[1 - L::cy[q]]);
+    const int vo = L::cx[q] > 0 ? t.vm : (L::cx[q] < 0 ? t.vp : t.vx);
+    g[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(src, vo, (int)so, 0));
+    qo += r.plane;
+  }
+}
+template <class L>
+__device__ inline void load_rows(rsrc_t src, const ItemRows& r, const Item& t, float v[L::Q]) {
+  unsigned qo = r.base;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    v[q] = __builtin_bit_cast(
+        float, __builtin_amdgcn_raw_buffer_load_b32(src, t.vx, (int)(qo + (r.z[1] + r.y[1])), 0));
+    qo += r.plane;
+  }
+}
+template <class L>
+__device__ inline void scatter_rows(rsrc_t dst, const ItemRows& r, const Item& t,
+                                    const float v[L::Q]) {
+  unsigned qo = r.base;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const unsigned so = qo + (r.z[1 - L::cz[q]] + r.y[1 - L::cy[q]]);
+    const int vo = L::cx[q] > 0 ? t.vm : (L::cx[q] < 0 ? t.vp : t.vx);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v[q]), dst, vo, (int)so, 0);
+    qo += r.plane;
+  }
+}
+
 template <class L, int q = 0>
 __device__ inline void gather_item(rsrc_t src, const Grid& G, const Item& t, float g[L::Q]) {
   if constexpr (q < L::Q) {
