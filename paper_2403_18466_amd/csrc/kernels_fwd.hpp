@@ -195,6 +195,16 @@ __device__ inline void load_rows(rsrc_t src, const ItemRows& r, const Item& t, f
     qo += r.plane;
   }
 }
+template <class L, int POLICY = 0>
+__device__ inline void store_rows(rsrc_t dst, const ItemRows& r, const Item& t, const float v[L::Q]) {
+  unsigned qo = r.base;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v[q]), dst, t.vx,
+                                          (int)(qo + (r.z[1] + r.y[1])), POLICY);
+    qo += r.plane;
+  }
+}
 template <class L>
 __device__ inline void scatter_rows(rsrc_t dst, const ItemRows& r, const Item& t,
                                     const float v[L::Q]) {
@@ -648,7 +658,10 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
   float gn[Q];
   if (it0 < ib1) {
     cur.start(it0, nxc, G);
-    gather_item<L>(src, G, cur.item(G, lane), gn);
+    {
+      const Item t0 = cur.item(G, lane);
+      gather_rows<L>(src, ItemRows(G, Q, t0), t0, gn);
+    }
   }
 
   // The weight fragments reach the registers through the (still unused)
@@ -685,13 +698,14 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
 #pragma unroll
     for (int q = 0; q < Q; ++q) X[lane * LD::SX + q] = gn[q];
     if (it + ST < ib1) {
+      nxt = cur;
       if constexpr (ST > 1) {
-        nxt.start(it + ST, nxc, G);
+        nxt.advance(ST, nxc, G);
       } else {
-        nxt = cur;
         nxt.next(nxc, G);
       }
-      gather_item<L>(src, G, nxt.item(G, lane), gn);
+      const Item tn = nxt.item(G, lane);
+      gather_rows<L>(src, ItemRows(G, Q, tn), tn, gn);
     }
     wave_lds_sync();
 #pragma unroll
@@ -739,7 +753,7 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
     if constexpr (FORCED) body_force(Fc, G, t.x, t.y, t.z, F3);
     float post[Q];
     finish_collision<L>(g, upd, rho, u, F3, FORCED, post);
-    if (t.active) store_local<L, kStoreNT>(dst, G, t, post);
+    if (t.active) store_rows<L, kStoreNT>(dst, ItemRows(G, Q, t), t, post);
     wave_lds_sync();
     cur = nxt;
   }
