@@ -147,20 +147,20 @@ __device__ inline float tanh_fast(float z) {
   return __builtin_fmaf(-2.f, __builtin_amdgcn_rcpf(1.f + e), 1.f);
 }
 
-// tanh to a few float32 ulps everywhere.  Near 0 the form above loses all
-// relative accuracy (1 - 2r cancels), so |z| < 0.55 uses
+// The float32 network's tanh is accurate to a few float32 ulps everywhere:
+// the exp form above for |z| >= 0.55, and below it (where 1 - 2r cancels and
+// loses all relative accuracy)
 //   tanh z = z + z^3 P(z^2),
 // with P the degree-4 least-squares fit of (tanh z - z) / z^3 in s = z^2,
 // weighted by s, on 4000 Chebyshev nodes of s in [0, 0.55^2] (max relative
 // error 6.4e-8 in float32); above it the exp form is within 2.9e-7.
-__device__ inline float tanh_accurate(float z) {
+__device__ inline float tanh_small(float z) {
   const float s = z * z;
   float p = __builtin_fmaf(-0.006272607482969761f, s, 0.02107025310397148f);
   p = __builtin_fmaf(p, s, -0.053851865231990814f);
   p = __builtin_fmaf(p, s, 0.13332580029964447f);
   p = __builtin_fmaf(p, s, -0.33333316445350647f);
-  const float small = __builtin_fmaf(z * s, p, z);
-  return __builtin_fabsf(z) < 0.55f ? small : tanh_fast(z);
+  return __builtin_fmaf(z * s, p, z);
 }
 
 // Scale of the tanh argument on the hardware exp2: e^{2z} = 2^{c z},
@@ -188,8 +188,35 @@ __device__ constexpr float tanh_weight_scale() {
 template <int P>
 __device__ inline f4 tanh4(f4 v) {
   f4 r;
+  if constexpr (P == P_F32) {
+    // |v| < 0.55 ? tanh_small(v) : tanh_fast(v) per value, with one
+    // wave-wide decision for the four values instead of a branch per value:
+    // where every lane's four values fall on one side of 0.55 only that
+    // side's form is evaluated, else both are and one is selected per value
+    bool small = true, big = true;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) r[k] = P == P_F32 ? tanh_accurate(v[k]) : tanh_prescaled(v[k]);
+    for (int k = 0; k < 4; ++k) {
+      const bool s = __builtin_fabsf(v[k]) < 0.55f;
+      small = small && s;
+      big = big && !s;
+    }
+    if (__builtin_amdgcn_ballot_w64(!small) == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) r[k] = tanh_small(v[k]);
+    } else if (__builtin_amdgcn_ballot_w64(!big) == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) r[k] = tanh_fast(v[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float a = tanh_small(v[k]), b = tanh_fast(v[k]);
+        r[k] = __builtin_fabsf(v[k]) < 0.55f ? a : b;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = tanh_prescaled(v[k]);
+  }
   return r;
 }
 
