@@ -346,10 +346,12 @@ __global__ __launch_bounds__(256) void moments_kernel(const float* __restrict__ 
 #pragma unroll
     for (int a = 0; a < 3; ++a) uv[a] = (j[a] + 0.5f * F[a]) * inv;
     const long long node = ((long long)t.z * G.ny + t.y) * G.nx + t.x;
-    if (rho) rho[(long long)b * G.plane + node] = r;
+    // the fields are written with the non-temporal policy, like the step
+    if (rho) __builtin_nontemporal_store(r, rho + (long long)b * G.plane + node);
     if (u) {
 #pragma unroll
-      for (int a = 0; a < L::D; ++a) u[((long long)b * L::D + a) * G.plane + node] = uv[a];
+      for (int a = 0; a < L::D; ++a)
+        __builtin_nontemporal_store(uv[a], u + ((long long)b * L::D + a) * G.plane + node);
     }
     if (finite) {
       double rd = r, uu = 0.0;
