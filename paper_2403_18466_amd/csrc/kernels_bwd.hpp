@@ -773,10 +773,10 @@ __device__ inline void stage_adjoint_weights(typename Frag<P>::T* bwd, typename 
 }
 
 // acc[j] += the product of tile CL::tile(W, j) over the slots (the nodes of
-// slots 2p and 2p + 1 form the K = 32 of one matrix-core instruction).  The
-// slot pairs are the outer loop, so an operand fragment that several of the
-// wavefront's tiles use is read once per pair; each tile still sums the
-// pairs in slot order.
+// slots 2p and 2p + 1 form the K = 32 of one matrix-core instruction).  An
+// operand fragment that several of the wavefront's tiles use is read once
+// per pair (with CL::PAIRS_OUTER the pairs are the outer loop, else the
+// compiler shares the reads); each tile sums the pairs in slot order.
 template <class CL, int P, int W>
 __device__ inline void coop_tiles(f4 (&acc)[CL::TPW], const unsigned char* slots, int rdo) {
   using Fr = typename Frag<P>::T;

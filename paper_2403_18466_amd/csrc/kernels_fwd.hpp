@@ -173,7 +173,8 @@ struct ItemRows {
   }
 };
 
-// gather_item, load_local and scatter_item with the rows of an ItemRows.
+// gather_item, load_local, store_local and scatter_item with the rows of an
+// ItemRows.
 template <class L>
 __device__ inline void gather_rows(rsrc_t src, const ItemRows& r, const Item& t, float g[L::Q]) {
   unsigned qo = r.base;
