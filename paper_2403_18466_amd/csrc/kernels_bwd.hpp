@@ -909,6 +909,12 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll
     for (int i = 0; i < N1; ++i) w1k[i] = W1F[64 * i + lane];
   }
+  // where all weights are in registers, the layer-2 bias c b2 is too
+  f4 b2k[RW1 ? S::HB : 1];
+  if constexpr (RW1) {
+#pragma unroll
+    for (int ob = 0; ob < S::HB; ++ob) b2k[ob] = *reinterpret_cast<const f4*>(b2s + 16 * ob + 4 * lg);
+  }
   // this lane's rows of a slot fragment: written, and read transposed
   const int wro = 8 * slot_row(lane), rdo = 8 * tr_row(lane);
 
@@ -1050,7 +1056,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
         }
 #pragma unroll
         for (int ob = 0; ob < S::HB; ++ob) {
-          const f4 b2 = *reinterpret_cast<const f4*>(b2s + 16 * ob + 4 * lg);
+          const f4 b2 = RW1 ? b2k[RW1 ? ob : 0] : *reinterpret_cast<const f4*>(b2s + 16 * ob + 4 * lg);
           t2[ob] = tanh4<P>(mma_row<P, S::HB>(b2, w2 + ob * S::HB, h1));
           h2[ob] = to_frag<P>(t2[ob]);
         }
