@@ -682,6 +682,20 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
     __syncthreads();
   }
   if (it0 >= ib1) return;
+  // the 16-bit instances hold the layer-3 bias in registers, in the MFMA
+  // result layout (rows 16 ob + 4 lg + r); the float32 ones, which have no
+  // registers to spare, read it from the tile's padding columns per group
+  constexpr bool B3R = P != P_F32;
+  f4 b3r[B3R ? S::QB : 1];
+  if constexpr (B3R) {
+#pragma unroll
+    for (int ob = 0; ob < S::QB; ++ob)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = 16 * ob + 4 * lg + r;
+        b3r[ob][r] = q < Q ? theta[S::ob3 + q] : 0.f;
+      }
+  }
 
   // the input columns past the populations never change: a constant 1 for
   // the bias of layer 1, then zeros
@@ -736,7 +750,8 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
         h2[ob] = to_frag<P>(tanh4<P>(mma_row<P, S::HB>(W.b2[ob], W.w2[ob], h1)));
 #pragma unroll
       for (int ob = 0; ob < S::QB; ++ob) {
-        const f4 b3 = *reinterpret_cast<const f4*>(X + (4 * ob + lg) * LD::SX + LD::B3);
+        const f4 b3 = B3R ? b3r[B3R ? ob : 0]
+                          : *reinterpret_cast<const f4*>(X + (4 * ob + lg) * LD::SX + LD::B3);
         const f4 y = mma_row<P, S::HB>(b3, W.w3[ob], h2);
         if (16 * ob + 4 * lg < LD::YQ)
           *reinterpret_cast<f4*>(Y + nrow * LD::SX + 16 * ob + 4 * lg) = y;
