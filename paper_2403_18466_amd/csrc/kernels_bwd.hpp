@@ -576,6 +576,27 @@ __device__ __host__ constexpr int slot_row(int l) { return l ^ (4 * (l >> 4)); }
 __device__ __host__ constexpr int tr_row(int L) {
   return slot_row(16 * ((L & 15) & 3) + 4 * (L >> 4) + ((L & 15) >> 2));
 }
+// The identity above, checked at compile time: with the transposing read's
+// lane rule for 16-bit elements (within a 16-lane block, lane 4 a + e takes
+// element e of the rows that lanes a + 4 j, j = 0..3, address), lane L's
+// value j is element e of the row written by the lane w with slot_row(w) =
+// tr_row(16 (L / 16) + a + 4 j), i.e. feature 4 (w / 16) + e of node w % 16;
+// it must be feature L % 16 of node 4 (L / 16) + j.
+__device__ __host__ constexpr bool slot_layout_ok() {
+  for (int L = 0; L < 64; ++L) {
+    const int blk = L >> 4, m = L & 15, a = m >> 2, e = m & 3;
+    for (int j = 0; j < 4; ++j) {
+      const int row = tr_row(16 * blk + a + 4 * j);
+      int w = -1;
+      for (int l = 0; l < 64; ++l)
+        if (slot_row(l) == row) w = l;
+      if (w < 0 || 4 * (w >> 4) + e != m || (w & 15) != 4 * blk + j) return false;
+    }
+  }
+  return true;
+}
+static_assert(slot_layout_ok(), "slot rows and transposing reads");
+
 template <int P>
 __device__ inline typename Frag<P>::T read_tr(const unsigned char* p) {
   typedef short v4s __attribute__((ext_vector_type(4)));
