@@ -596,6 +596,21 @@ __device__ __host__ constexpr bool slot_layout_ok() {
   return true;
 }
 static_assert(slot_layout_ok(), "slot rows and transposing reads");
+// and the swizzle's purpose: an 8-byte row sits on bank pair row % 16, so
+// the 16 rows that a 16-lane block reads, and those that 16 consecutive
+// lanes write, must fall on 16 different pairs
+__device__ __host__ constexpr bool slot_banks_ok() {
+  for (int blk = 0; blk < 4; ++blk) {
+    int rd = 0, wr = 0;
+    for (int i = 0; i < 16; ++i) {
+      rd |= 1 << (tr_row(16 * blk + i) & 15);
+      wr |= 1 << (slot_row(16 * blk + i) & 15);
+    }
+    if (rd != 0xffff || wr != 0xffff) return false;
+  }
+  return true;
+}
+static_assert(slot_banks_ok(), "slot rows on distinct bank pairs");
 
 template <int P>
 __device__ inline typename Frag<P>::T read_tr(const unsigned char* p) {
