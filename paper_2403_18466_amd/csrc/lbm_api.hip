@@ -347,8 +347,9 @@ lbm_status launch_bgk_v(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t
 
 template <class L>
 lbm_status launch_bgk(lbm_ctx* ctx, const float* Ain, float* Aout, hipStream_t s) {
-  // one node per thread with non-temporal stores measured fastest (more rows
-  // per thread lowered the achieved bandwidth)
+  // one node per thread with non-temporal stores measured fastest for both
+  // lattices (D3Q19 256^3: 452 us; two rows per thread 459 us, default
+  // stores 474 us)
   if (ctx->cfg.collision == LBM_COLLISION_SMAGORINSKY)
     return launch_bgk_v<L, 1, true, true>(ctx, Ain, Aout, s);
   return launch_bgk_v<L, 1, true, false>(ctx, Ain, Aout, s);
