@@ -990,14 +990,25 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   // position and loads and stores nothing).
   ItemWalk wcur, wnxt;
   wcur.start(ib0 + wave, nxc, G);
-  float gc[Q], mc[Q];
-  if (ib0 < ib1) load(ib0 + wave, wcur, gc, mc);
+  // The body force of an item is read before the stores of the previous
+  // item (see wait_vmem): with the item's populations for D2Q9, at the end
+  // of the previous item for D3Q19, whose registers (251 of 256) cannot hold
+  // it across the groups without spilling.
+  constexpr bool FORCE_EARLY = L::Q == 9;
+  float gc[Q], mc[Q], F3[3] = {0.f, 0.f, 0.f};
+  if (ib0 < ib1) {
+    load(ib0 + wave, wcur, gc, mc);
+    if (Fc.kind != 0) {
+      const Item t0 = wcur.item(G, lane);
+      body_force(Fc, G, t0.x, t0.y, t0.z, F3);
+    }
+  }
+  // no wait in the loop has to cover the loads issued before it
+  wait_vmem();
   for (int k = ib0; k < ib1; k += NW) {
     const int it = k + wave;
     const Item t = wcur.item(G, lane);
     const bool act = it < ib1 && t.active;
-    float F3[3] = {0.f, 0.f, 0.f};
-    if (Fc.kind != 0) body_force(Fc, G, t.x, t.y, t.z, F3);
     float nu[Q], lam[Q];
     collide_adjoint<L>(gc, mc, rho0, omega, F3, Fc.kind != 0, nu, lam);
 
@@ -1049,7 +1060,13 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
     // the next item's loads are in flight while this item's network runs
     wnxt = wcur;
     wnxt.advance(NW, nxc, G);
-    if (k + NW < ib1) load(it + NW, wnxt, gc, mc);
+    if (k + NW < ib1) {
+      load(it + NW, wnxt, gc, mc);
+      if (FORCE_EARLY && Fc.kind != 0) {
+        const Item tn = wnxt.item(G, lane);
+        body_force(Fc, G, tn.x, tn.y, tn.z, F3);
+      }
+    }
 
     // a D-layout fragment to the slot: lane l's four values to row slot_row(l)
     auto put_t = [&](int f, Fr v) { *reinterpret_cast<Fr*>(slot + f * 512 + wro) = v; };
@@ -1179,6 +1196,12 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll
       for (int q = 0; q < Q; ++q) lam[q] += D[lane * CL::SD + q];
     }
+    if (!FORCE_EARLY && Fc.kind != 0 && k + NW < ib1) {
+      const Item tn = wnxt.item(G, lane);
+      body_force(Fc, G, tn.x, tn.y, tn.z, F3);
+    }
+    // the next item's loads arrived during the groups
+    wait_vmem();
     if (act) scatter_rows<L>(rL0, ItemRows(G, Q, t), t, lam);
     wave_lds_sync();
     wcur = wnxt;

@@ -559,6 +559,15 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Waits until every vector-memory access the wavefront has issued is done
+// (s_waitcnt vmcnt(0); the export and LDS counters are not waited on).  One
+// counter covers loads and stores, and the compiler cannot assume that they
+// complete in order: a wait for a load issued before a burst of stores also
+// waits for the stores to be acknowledged.  Called just before such a burst,
+// when the loads issued earlier have long arrived, it costs nothing and
+// leaves the stores in flight past the later uses of those loads.
+__device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // ---------------------------------------------------------------------------
 // Learned-collision stream-collide (eq. nn-model-full with the kappa layer).
 //
@@ -709,6 +718,9 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
     }
   }
 
+  // the biases and the first item's populations have arrived: no wait in the
+  // loop has to cover loads issued before it
+  wait_vmem();
   for (int it = it0; it < ib1; it += ST) {
     // this item's populations go to the LDS tile; the next item's loads are
     // issued before the network runs
@@ -723,6 +735,12 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
       }
       const Item tn = nxt.item(G, lane);
       gather_rows<L>(src, ItemRows(G, Q, tn), tn, gn);
+    }
+    // the body force is read here, so that it arrives while the network runs
+    float F3[3] = {0.f, 0.f, 0.f};
+    if constexpr (FORCED) {
+      const Item tc = cur.item(G, lane);
+      body_force(Fc, G, tc.x, tc.y, tc.z, F3);
     }
     wave_lds_sync();
 #pragma unroll
@@ -767,10 +785,10 @@ __attribute__((amdgpu_waves_per_eu(StepLds<L, H>::min_waves(P, FORCED)))) void n
     bgk_update<L>(g, rho0, omega, upd, rho, u);
 #pragma unroll
     for (int q = 0; q < Q; ++q) upd[q] = __builtin_fmaf(knn, Y[lane * LD::SX + q], upd[q]);
-    float F3[3] = {0.f, 0.f, 0.f};
-    if constexpr (FORCED) body_force(Fc, G, t.x, t.y, t.z, F3);
     float post[Q];
     finish_collision<L>(g, upd, rho, u, F3, FORCED, post);
+    // the next item's populations arrived while the network ran
+    wait_vmem();
     if (t.active) store_rows<L, kStoreNT>(dst, ItemRows(G, Q, t), t, post);
     wave_lds_sync();
     cur = nxt;
