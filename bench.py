@@ -61,7 +61,7 @@ ADJ_ACT_PEAK_LUPS = SIMD_CYCLES / ADJ_ACT_CYCLES_PER_LUP
 # HBM bytes per launch of the bf16 step from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # each scaled by the factor a plain copy of known size gives (2.000 / 1.000);
 # None until taken for the current kernel (profiles/).
-TRAFFIC_BYTES = 1.2276e9
+TRAFFIC_BYTES = 1.2294e9
 
 
 def parse():
