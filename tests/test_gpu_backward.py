@@ -134,6 +134,8 @@ def test_nlbm_adjoint_reduced_precision(lbm, prec):
     ("D2Q9", "bf16", 32, (1, 64, 200), 2, 0),
     ("D2Q9", "fp16", 32, (1, 33, 70), 2, 1),    # fewer items than workgroups
     ("D3Q19", "bf16", 32, (9, 10, 70), 2, 2),   # 360 items, three-component force, compact staging
+    ("D3Q19", "bf16", 64, (16, 16, 70), 5, 2),  # 2560 items: two on some wavefronts, whose force is
+                                                # read at the end of their first
     ("D3Q19", "fp16", 64, (6, 7, 20), 1, 0),    # the cooperative kernel, compact staging
 ])
 def test_nlbm_adjoint_16bit_per_block(lbm, lat, prec, H, shape, batch, force):
