@@ -185,13 +185,14 @@ def time_kolmogorov(torch, lbm, inputs, steps):
     return res
 
 
-def time_training(torch, lbm, inputs, prec, reps):
+def time_training(torch, lbm, inputs, prec, reps, ckpt=8):
     """One training step of the unrolled-training workload: 8 fields of
     256 x 256, 32 unrolled steps with a checkpoint every 8 (forward, segment
     recompute, 32 adjoint steps, loss gradient, Adam), tau' = 0.50125,
     network 9->64->64->9.  Inputs are synthetic (equilibria of random
     solenoidal fields); returns the median wall time of `reps` steps and the
-    adjoint-kernel throughput."""
+    adjoint-kernel throughput.  ckpt = 32 keeps the whole trajectory (31
+    states of 18.9 MB) and recomputes nothing."""
     from paper_2403_18466_amd import training
     import numpy as np
     n, B = 256, 8
@@ -209,7 +210,7 @@ def time_training(torch, lbm, inputs, prec, reps):
     for r in range(reps + 2):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        loss, dth, _ = training.unrolled_loss_and_grad(L, A0, theta, ut, 32, 8)
+        loss, dth, _ = training.unrolled_loss_and_grad(L, A0, theta, ut, 32, ckpt)
         opt.step(dth)
         torch.cuda.synchronize()
         if r >= 2:
@@ -696,10 +697,18 @@ def training_leg(torch, lbm, inputs):
     for p, v in tr.items():
         print(f"# training step {p}: {v['train_step_ms']:.2f} ms, adjoint "
               f"{v['adjoint_mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    # the same gradient with the whole trajectory kept in HBM (no recompute)
+    keep = time_training(torch, lbm, inputs, "bf16", 5, ckpt=32)
+    print(f"# training step bf16, whole trajectory kept: {keep['train_step_ms']:.2f} ms",
+          file=sys.stderr, flush=True)
     lups = tr["bf16"]["adjoint_mlups"] * 1e6
     return {"workload": "8 x 256^2 D2Q9, 32 unrolled steps, checkpoint every 8, H=64, "
                         "forward + recompute + adjoint + Adam",
             **{p: v for p, v in tr.items()},
+            "bf16_keep_all": {"train_step_ms": keep["train_step_ms"],
+                              "workload": "the same 32 steps with every state kept (one segment "
+                                          "of 32, 31 x 18.9 MB): no recompute, one gradient "
+                                          "reduction"},
             "bf16_over_fp32_step_time": tr["fp32"]["train_step_ms"] / tr["bf16"]["train_step_ms"],
             "adjoint_roofline": {
                 "kernel": "nlbm_backward_coop_kernel<D2Q9, 64, bf16> + grad_reduce_kernel",
