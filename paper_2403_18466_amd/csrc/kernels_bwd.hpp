@@ -967,8 +967,17 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   const unsigned bytes = (unsigned)G.plane * (unsigned)(G.batch * Q) * 4u;
   const rsrc_t rA = make_rsrc(A, bytes), rL1 = make_rsrc(lam1, bytes),
                rL0 = make_rsrc(lam0, bytes);
-  // items past the range enter as zeros: every product they feed is zero
-  auto load = [&](int it, const ItemWalk& w, float g[Q], float mu[Q]) {
+  // The next item's loads go out in two halves: the pulled populations
+  // before the groups, lam^{n+1} with the second group.  Issued at once, the
+  // 2 Q loads of all the workgroup's wavefronts kept them waiting for the
+  // address unit (1.5 us per item measured for D3Q19).
+  // part 1: the pulled populations, 2: lam^{n+1}, 3: both.  Nodes past the
+  // range enter as zeros (every product they feed is zero): mu is zeroed
+  // where the item starts (zeroing it here, inside the group loop, made the
+  // compiler wait there for the loads in flight), g there too for D2Q9 and
+  // here for D3Q19, the faster placement for each in alternating runs.
+  constexpr bool G_AT_START = L::Q == 9;
+  auto load = [&](int it, const ItemWalk& w, float g[Q], float mu[Q], int part) {
     bool act = false;
     Item t;
     if (it < ib1) {
@@ -977,11 +986,11 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
     }
     if (act) {
       const ItemRows r(G, Q, t);
-      gather_rows<L>(rA, r, t, g);
-      load_rows<L>(rL1, r, t, mu);
-    } else {
+      if (part & 1) gather_rows<L>(rA, r, t, g);
+      if (part & 2) load_rows<L>(rL1, r, t, mu);
+    } else if (!G_AT_START && (part & 1)) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) g[q] = mu[q] = 0.f;
+      for (int q = 0; q < Q; ++q) g[q] = 0.f;
     }
   };
 
@@ -997,7 +1006,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   constexpr bool FORCE_EARLY = L::Q == 9;
   float gc[Q], mc[Q], F3[3] = {0.f, 0.f, 0.f};
   if (ib0 < ib1) {
-    load(ib0 + wave, wcur, gc, mc);
+    load(ib0 + wave, wcur, gc, mc, 3);
     if (Fc.kind != 0) {
       const Item t0 = wcur.item(G, lane);
       body_force(Fc, G, t0.x, t0.y, t0.z, F3);
@@ -1009,6 +1018,13 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
     const int it = k + wave;
     const Item t = wcur.item(G, lane);
     const bool act = it < ib1 && t.active;
+    if (!act) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        mc[q] = 0.f;
+        if (G_AT_START) gc[q] = 0.f;
+      }
+    }
     float nu[Q], lam[Q];
     collide_adjoint<L>(gc, mc, rho0, omega, F3, Fc.kind != 0, nu, lam);
 
@@ -1061,7 +1077,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
     wnxt = wcur;
     wnxt.advance(NW, nxc, G);
     if (k + NW < ib1) {
-      load(it + NW, wnxt, gc, mc);
+      load(it + NW, wnxt, gc, mc, 1);
       if (FORCE_EARLY && Fc.kind != 0) {
         const Item tn = wnxt.item(G, lane);
         body_force(Fc, G, tn.x, tn.y, tn.z, F3);
@@ -1073,6 +1089,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll 1
     for (int jg = 0; jg < 4; ++jg) {
       const int nrow = 16 * jg + li;
+      if (jg == 1 && k + NW < ib1) load(it + NW, wnxt, gc, mc, 2);
       // Weight fragments read from LDS come as one batch per layer, issued
       // before the VALU work of the previous layer so that their latency
       // overlaps it (the scheduling barriers keep the reads there).
