@@ -968,9 +968,10 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
   const rsrc_t rA = make_rsrc(A, bytes), rL1 = make_rsrc(lam1, bytes),
                rL0 = make_rsrc(lam0, bytes);
   // The next item's loads go out in two halves: the pulled populations
-  // before the groups, lam^{n+1} with the second group.  Issued at once, the
-  // 2 Q loads of all the workgroup's wavefronts kept them waiting for the
-  // address unit (1.5 us per item measured for D3Q19).
+  // before the groups, lam^{n+1} with the second group (for D3Q19, with the
+  // second or the third, odd and even wavefronts taking turns).  Issued at
+  // once, the 2 Q loads of all the workgroup's wavefronts kept them waiting
+  // for the address unit (1.5 us per item measured for D3Q19).
   // part 1: the pulled populations, 2: lam^{n+1}, 3: both.  Nodes past the
   // range enter as zeros (every product they feed is zero): mu is zeroed
   // where the item starts (zeroing it here, inside the group loop, made the
@@ -1089,7 +1090,7 @@ nlbm_backward_coop_kernel(const float* __restrict__ A, const float* __restrict__
 #pragma unroll 1
     for (int jg = 0; jg < 4; ++jg) {
       const int nrow = 16 * jg + li;
-      if (jg == 1 && k + NW < ib1) load(it + NW, wnxt, gc, mc, 2);
+      if (jg == (L::Q == 9 ? 1 : 1 + (wave & 1)) && k + NW < ib1) load(it + NW, wnxt, gc, mc, 2);
       // Weight fragments read from LDS come as one batch per layer, issued
       // before the VALU work of the previous layer so that their latency
       // overlaps it (the scheduling barriers keep the reads there).
